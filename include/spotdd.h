@@ -1,0 +1,258 @@
+/*
+ * spotdd.h -- C ABI of libspotdd: brute-force incoherent dedispersion of an
+ * 8-bit multichannel filterbank over many trial dispersion measures (DMs),
+ * followed by a boxcar matched-filter single-pulse S/N search, on one
+ * AMD Instinct MI355X (gfx950) GPU.
+ *
+ * Method (paper: "Searching For Fast Radio Transients And Radio Pulsars Using
+ * SPOTLIGHT"):
+ *   - Chapter 1, Eq. (1): the dispersion delay of channel frequency f at
+ *     dispersion measure DM, relative to the top frequency, is proportional
+ *     to DM * (f^-2 - f_top^-2).
+ *   - Section 3.2: brute-force dedispersion sums all channels of the dynamic
+ *     spectrum along that delay curve, per trial DM; the series may be
+ *     downsampled by a user factor.
+ *   - Section 2.1: many trial DMs are dedispersed, then a single-pulse search
+ *     by time-domain boxcar filtering reports pulses above a user threshold.
+ *
+ * Conventions the paper leaves open (fixed here and used by every call):
+ *   delay   d(c,i) = floor(v + 0.5), v = 4.148808e3 * DM_i * (1/(f_c*f_c) -
+ *           1/(f_top*f_top)) / (dec * t_samp), FP64, evaluated left to right;
+ *           f in MHz, t_samp in s, f_top = max listed frequency.
+ *   decim.  a DM range with decimation dec > 1 dedisperses the exact sums of
+ *           dec consecutive input samples (groups aligned to input sample 0).
+ *   extent  O = max_r (maxdelay_r + w_max - 1) * dec_r native samples
+ *           (w_max = 1 with no widths). For nsamp_in input samples the call
+ *           owns N = nsamp_in - O native samples; range r owns
+ *           N_r = N / dec_r (floor) samples and its plane has
+ *           cols_r = N_r + w_max - 1 columns:
+ *           plane_r[i][j] = sum_c x_r[c][j + d_r(c,i)], j < cols_r (uint32,
+ *           exact).
+ *   search  for owned start j < N_r and width w: B_w[j] = sum_{k<w} y[j+k];
+ *           S/N = (B_w[j] - w*mu) / (sigma*sqrt(w)) in FP64, mu = S1/n,
+ *           sigma = sqrt(n*S2 - S1^2)/n, n = N_r, S1/S2 the exact sums of y and
+ *           y^2 over the owned samples. A constant series (n*S2 == S1^2) has
+ *           S/N 0 everywhere and no candidate. Best = first maximum in
+ *           (j ascending, w ascending) order. A candidate is the best of one
+ *           cell of cand_block owned starts, kept if S/N > threshold
+ *           (strict); candidates are ordered by (range, DM index, sample).
+ *
+ * General rules:
+ *   - Every call returns sdd_status (0 = ok, < 0 = error); nothing throws
+ *     across the ABI. sdd_last_error() returns a thread-local message for the
+ *     last failing call on the calling thread.
+ *   - "d_" pointers are device pointers on the plan's device; "host_"
+ *     pointers are host memory. The caller owns every buffer it passes.
+ *   - stream is a hipStream_t (NULL = the null stream). Compute calls only
+ *     enqueue work; results are valid once the stream has been synchronised.
+ *   - Integer sums are exact by construction: plan creation refuses (ERANGE)
+ *     a plan whose plane sums could exceed 2^32 - 1 or whose S2 could exceed
+ *     2^64 - 1 (the latter is also checked per call against N_r).
+ */
+#ifndef SPOTDD_H
+#define SPOTDD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SDD_ABI_VERSION 1
+#define SDD_MAX_RANGES 16
+#define SDD_MAX_WIDTHS 32
+#define SDD_MAX_WMAX 8192
+
+typedef enum sdd_status {
+  SDD_OK = 0,
+  SDD_EINVAL = -1,    /* bad argument: null pointer, size, ordering, layout */
+  SDD_ERANGE = -2,    /* exact integer sums could overflow */
+  SDD_ENOMEM = -3,    /* workspace too small, or device allocation failed */
+  SDD_EDEVICE = -4,   /* HIP error; message in sdd_last_error() */
+  SDD_EAGAIN = -5,    /* (server) no room now: retry later */
+  SDD_ESTATE = -6,    /* (server) call out of order: sequence gap, closed stream */
+  SDD_ETIMEDOUT = -7  /* (server) poll timed out with no result */
+} sdd_status;
+
+/* Input layouts. Time-major is the spectra order a beamformer writes
+ * (Section 2.2): byte (t, c) at d_in[t * in_pitch + c]. Channel-major:
+ * byte (c, t) at d_in[c * in_pitch + t]. */
+enum { SDD_CHAN_MAJOR = 0, SDD_TIME_MAJOR = 1 };
+
+/* One DM range: DM_i = lo + i*step (FP64) for i < floor((hi-lo)/step + 0.5),
+ * dedispersed at time decimation `decimation` (>= 1). */
+typedef struct sdd_dm_range {
+  double dm_lo, dm_hi, dm_step;
+  int32_t decimation;
+  int32_t reserved;
+} sdd_dm_range;
+
+typedef struct sdd_plan_desc {
+  const double* freqs_mhz;     /* [nchan] channel centre frequencies, any order, > 0 */
+  const double* dm_list;       /* [ndm] explicit trial DMs (>= 0, decimation 1), or NULL */
+  const sdd_dm_range* ranges;  /* [nranges] DM ranges, or NULL; exactly one of the two */
+  const int32_t* widths;       /* [nwidths] boxcar widths, strictly ascending, >= 1;
+                                  nwidths == 0: plane only, no search */
+  double t_samp_s;             /* native sampling time, > 0 */
+  int32_t nchan;               /* >= 1 */
+  int32_t ndm;                 /* entries of dm_list */
+  int32_t nranges;             /* entries of ranges, <= SDD_MAX_RANGES */
+  int32_t nwidths;             /* <= SDD_MAX_WIDTHS, w_max <= SDD_MAX_WMAX */
+  int32_t cand_block;          /* owned starts per candidate cell, >= 1 (0: 1024) */
+  float threshold;             /* candidate when S/N > threshold */
+  int32_t layout;              /* SDD_CHAN_MAJOR or SDD_TIME_MAJOR */
+  int32_t device;              /* HIP device ordinal */
+} sdd_plan_desc;
+
+typedef struct sdd_plan sdd_plan;
+
+typedef struct sdd_plan_info {
+  int32_t nchan, nranges, ndm_total, nwidths;
+  int32_t w_max, cand_block, layout, device;
+  int64_t overlap;                         /* O, native samples */
+  int32_t ndm[SDD_MAX_RANGES];             /* trials per range */
+  int32_t dm_offset[SDD_MAX_RANGES];       /* global index of the range's first trial */
+  int32_t decimation[SDD_MAX_RANGES];
+  int32_t max_delay[SDD_MAX_RANGES];       /* largest delay of the range, its own samples */
+} sdd_plan_info;
+
+/* Per-call sizes for nsamp_in input samples. */
+typedef struct sdd_geometry {
+  int64_t nsamp_in, overlap, n_owned;      /* n_owned = N = nsamp_in - O */
+  int64_t n_owned_r[SDD_MAX_RANGES];       /* N_r */
+  int64_t plane_cols[SDD_MAX_RANGES];      /* N_r + w_max - 1 */
+  int64_t ncells[SDD_MAX_RANGES];          /* ceil(N_r / cand_block), 0 without widths */
+  int64_t workspace_bytes;                 /* caller passes its own planes */
+  int64_t workspace_bytes_planes;          /* planes live inside the workspace */
+} sdd_geometry;
+
+typedef struct sdd_candidate {
+  int32_t range;      /* DM range */
+  int32_t dm_index;   /* trial index within the range */
+  int64_t sample;     /* window start j, in the range's own (decimated) samples */
+  int32_t width;      /* boxcar width, the range's own samples */
+  float snr;          /* S/N (FP64 rounded to float) */
+} sdd_candidate;
+
+typedef struct sdd_dm_best {   /* best (S/N, j, w) of one trial over all owned starts */
+  float snr;
+  int32_t width;
+  int64_t sample;
+} sdd_dm_best;
+
+typedef struct sdd_dm_stats {  /* moments of the owned samples of one trial */
+  int64_t n;
+  uint64_t s1, s2;
+  double mean, std;
+} sdd_dm_stats;
+
+/* Tile shape of the dedispersion kernel (a fixed menu; see sdd_tile_menu).
+ * kind 0: direct kernel (one thread per DM and 4 samples, no LDS);
+ * kind 1: LDS-tiled kernel. The other fields apply to kind 1. */
+typedef struct sdd_tile {
+  int32_t kind;
+  int32_t dm_per_wave;     /* DM trials per wavefront */
+  int32_t waves_dm;        /* wavefronts along DM per workgroup */
+  int32_t waves_time;      /* wavefronts along time per workgroup */
+  int32_t pairs_per_lane;  /* 2-sample pairs per lane (samples per lane / 2) */
+  int32_t chan_stage;      /* channels staged in LDS per step */
+} sdd_tile;
+
+/* ---- library ------------------------------------------------------------ */
+
+/* ABI version (SDD_ABI_VERSION of the built library). */
+int32_t sdd_abi_version(void);
+/* Message of the last failing call on this thread ("" if none). The pointer
+ * stays valid until the next sdd_* call on the same thread. */
+const char* sdd_last_error(void);
+/* Static name of a status code. */
+const char* sdd_status_string(int32_t status);
+
+/* ---- plan (host only: these calls touch no GPU) -------------------------- */
+
+/* Builds the FP64 delay tables (Chapter 1, Eq. (1)), the overlap and the
+ * exactness guards. Copies everything it needs from desc. EINVAL on a bad
+ * descriptor, ERANGE on an overflow risk. *out is owned by the caller and
+ * freed with sdd_plan_destroy. */
+sdd_status sdd_plan_create(const sdd_plan_desc* desc, sdd_plan** out);
+/* Frees the plan and its device tables. NULL is accepted. The caller must not
+ * destroy a plan with work still in flight that uses it. */
+sdd_status sdd_plan_destroy(sdd_plan* plan);
+sdd_status sdd_plan_query(const sdd_plan* plan, sdd_plan_info* out);
+/* Copies range r's delay table, int32 [ndm_r][nchan] row-major, to host_out. */
+sdd_status sdd_plan_delays(const sdd_plan* plan, int32_t range, int32_t* host_out);
+/* Copies range r's trial DMs, double [ndm_r], to host_out. */
+sdd_status sdd_plan_dms(const sdd_plan* plan, int32_t range, double* host_out);
+/* Sizes for nsamp_in samples. EINVAL if nsamp_in < O + dec_max (some range
+ * would own no sample); ERANGE if S2 could overflow at that length. */
+sdd_status sdd_plan_geometry(const sdd_plan* plan, int64_t nsamp_in, sdd_geometry* out);
+/* Tile used for range r (set by the heuristic, sdd_plan_set_tile or
+ * sdd_autotune). */
+sdd_status sdd_plan_get_tile(const sdd_plan* plan, int32_t range, sdd_tile* out);
+/* Forces range r's tile (range -1: every range). EINVAL if the shape is not
+ * in the built menu or cannot hold the range's delay span. Results never
+ * depend on the tile: the sums are exact. */
+sdd_status sdd_plan_set_tile(sdd_plan* plan, int32_t range, const sdd_tile* tile);
+/* Writes up to max menu entries to host_out; *n_out = menu size. */
+sdd_status sdd_tile_menu(sdd_tile* host_out, int32_t max, int32_t* n_out);
+
+/* ---- compute (enqueue on stream) ---------------------------------------- */
+
+/* Dedisperses one chunk (Section 3.2, Section 2.1): corner turn (time-major
+ * input), decimation (ranges with dec > 1), then every range's plane.
+ *   d_in       uint8 input, layout as planned, nsamp_in samples per channel
+ *   in_pitch   bytes between rows (time-major: >= nchan; channel-major:
+ *              >= nsamp_in)
+ *   d_planes   [nranges] device pointers (host array) to uint32 planes
+ *              [ndm_r][plane_pitch[r]]; plane_pitch[r] >= cols_r elements
+ *   d_workspace / ws_bytes: device scratch, >= geometry.workspace_bytes
+ * The call uploads the plan's delay tables on first use on a device
+ * (a synchronous copy). */
+sdd_status sdd_dedisperse(const sdd_plan* plan, const uint8_t* d_in, int64_t nsamp_in,
+                          int64_t in_pitch, uint32_t* const* d_planes,
+                          const int64_t* plane_pitch, void* d_workspace, int64_t ws_bytes,
+                          void* stream);
+
+/* Single-pulse boxcar search (Section 2.1) of planes made by sdd_dedisperse
+ * for the same nsamp_in.
+ *   d_best   [ndm_total] per-trial best (global trial order: range by range)
+ *   d_stats  [ndm_total] per-trial moments (may be NULL)
+ *   d_cands  [cap] candidates in (range, dm, sample) order; *d_ncand receives
+ *            the total number found, which may exceed cap (only the first
+ *            cap are written)
+ * EINVAL if the plan has no widths. */
+sdd_status sdd_search_boxcar(const sdd_plan* plan, const uint32_t* const* d_planes,
+                             const int64_t* plane_pitch, int64_t nsamp_in,
+                             sdd_dm_best* d_best, sdd_dm_stats* d_stats,
+                             sdd_candidate* d_cands, int32_t cap, int32_t* d_ncand,
+                             void* d_workspace, int64_t ws_bytes, void* stream);
+
+/* sdd_dedisperse followed by sdd_search_boxcar. d_planes may be NULL: the
+ * planes then live in the workspace (>= geometry.workspace_bytes_planes) and
+ * are not returned. */
+sdd_status sdd_dedisperse_search(const sdd_plan* plan, const uint8_t* d_in, int64_t nsamp_in,
+                                 int64_t in_pitch, uint32_t* const* d_planes,
+                                 const int64_t* plane_pitch, sdd_dm_best* d_best,
+                                 sdd_dm_stats* d_stats, sdd_candidate* d_cands, int32_t cap,
+                                 int32_t* d_ncand, void* d_workspace, int64_t ws_bytes,
+                                 void* stream);
+
+/* ---- kernel timing (benchmarks) ----------------------------------------- */
+
+/* Stages whose kernels can be timed. */
+enum { SDD_STAGE_CORNER_TURN = 0, SDD_STAGE_DECIMATE = 1, SDD_STAGE_DEDISPERSE = 2,
+       SDD_STAGE_SEARCH = 3, SDD_NSTAGES = 4 };
+
+/* on != 0: from now on every stage launch is bracketed by two HIP events
+ * recorded on the launch stream; the accumulated times are reset. on == 0:
+ * stops recording (pending events are still read by sdd_profile_read).
+ * Process-wide; not for concurrent use from several threads. */
+sdd_status sdd_profile_enable(int32_t on);
+/* Waits for the recorded events and returns the summed GPU time (ms) and the
+ * number of launches of one stage since the last enable. */
+sdd_status sdd_profile_read(int32_t stage, double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPOTDD_H */

@@ -79,11 +79,12 @@ def delay_table(freqs_mhz: Sequence[float], dms: Sequence[float], t_samp: float,
 def decimate(x: np.ndarray, dec: int) -> np.ndarray:
     """Section 3.2 downsampling as an exact sum of dec consecutive samples
     (R4): out[c][j] = sum_{k<dec} x[c][j*dec + k], j < T // dec. int64."""
-    x = np.asarray(x).astype(np.int64)
+    x = np.asarray(x)
     if dec == 1:
-        return x
+        return x.astype(np.int64)
     n = x.shape[1] // dec
-    return x[:, : n * dec].reshape(x.shape[0], n, dec).sum(axis=2)
+    # int32 holds any sum of dec <= 2^23 uint8/uint16 values exactly
+    return x[:, : n * dec].reshape(x.shape[0], n, dec).sum(axis=2, dtype=np.int32)
 
 
 def corner_turn(x_time_major: np.ndarray) -> np.ndarray:
@@ -104,7 +105,7 @@ def dedisperse(xr: np.ndarray, delays: np.ndarray, length: int) -> np.ndarray:
 
 def dedisperse_rows(xr: np.ndarray, delays: np.ndarray, rows, length: int) -> np.ndarray:
     """dedisperse() restricted to the given DM rows (same sum, one row at a time)."""
-    xr = np.asarray(xr).astype(np.int64)
+    xr = np.asarray(xr)  # uint8/int32 rows are added into int64 sums below
     rows = list(rows)
     nchan = xr.shape[0]
     y = np.zeros((len(rows), length), dtype=np.int64)
@@ -264,7 +265,7 @@ def run(plan: PlanSpec, x: np.ndarray, rows: Optional[List[Sequence[int]]] = Non
     owned = plan.owned(x.shape[1])
     out = []
     for r, spec in enumerate(plan.ranges):
-        xr = decimate(x, spec.dec)
+        xr = x if spec.dec == 1 else decimate(x, spec.dec)
         length = owned[r] + plan.w_max - 1
         rr = list(range(len(spec.dms))) if rows is None else list(rows[r])
         y = dedisperse_rows(xr, spec.delays, rr, length)

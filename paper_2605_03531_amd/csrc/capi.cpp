@@ -1,0 +1,260 @@
+// extern "C" compute entry points of libspotdd: argument checks, workspace
+// carving and the launch sequence of one chunk (corner turn -> decimation ->
+// dedispersion per range -> boxcar search).
+#include <algorithm>
+#include <cstring>
+
+#include "sdd_internal.h"
+
+namespace sdd {
+const char* last_error();
+
+namespace {
+
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && hipSetDevice(dev) == hipSuccess) ok = true;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+sdd_status check_planes(const sdd_plan* p, const CallGeom& cg, const void* const* planes,
+                        const int64_t* pitch) {
+  if (!planes || !pitch) SDD_FAIL(SDD_EINVAL, "null plane array or pitch array");
+  for (size_t r = 0; r < p->ranges.size(); ++r) {
+    if (!planes[r]) SDD_FAIL(SDD_EINVAL, "null plane for range %zu", r);
+    if (pitch[r] < cg.g.plane_cols[r])
+      SDD_FAIL(SDD_EINVAL, "range %zu: plane pitch %lld < %lld columns", r, (long long)pitch[r],
+               (long long)cg.g.plane_cols[r]);
+  }
+  return SDD_OK;
+}
+
+sdd_status check_input(const sdd_plan* p, const uint8_t* d_in, int64_t nsamp_in,
+                       int64_t in_pitch) {
+  if (!d_in) SDD_FAIL(SDD_EINVAL, "null input");
+  if (p->layout == SDD_TIME_MAJOR && in_pitch < p->nchan)
+    SDD_FAIL(SDD_EINVAL, "time-major pitch %lld < nchan %d", (long long)in_pitch, p->nchan);
+  if (p->layout == SDD_CHAN_MAJOR && in_pitch < nsamp_in)
+    SDD_FAIL(SDD_EINVAL, "channel-major pitch %lld < nsamp_in %lld", (long long)in_pitch,
+             (long long)nsamp_in);
+  return SDD_OK;
+}
+
+sdd_status run_dedisperse(const sdd_plan* p, const CallGeom& cg, const uint8_t* d_in,
+                          int64_t nsamp_in, int64_t in_pitch, uint32_t* const* planes,
+                          const int64_t* pitch, uint8_t* ws, hipStream_t s) {
+  const WsLayout& L = cg.ws;
+  const uint8_t* src = d_in;
+  int64_t src_pitch = in_pitch;
+  if (p->layout == SDD_TIME_MAJOR) {
+    uint8_t* ct = ws + L.ct_off;
+    StageTimer tm(SDD_STAGE_CORNER_TURN, s);
+    SDD_HIP_TRY(launch_corner_turn(d_in, nsamp_in, in_pitch, p->nchan, ct, L.ct_pitch, s));
+    src = ct;
+    src_pitch = L.ct_pitch;
+  }
+  // each decimation is built from the largest smaller one that divides it
+  std::vector<uint16_t*> dbuf(L.decs.size());
+  for (size_t k = 0; k < L.decs.size(); ++k) {
+    dbuf[k] = reinterpret_cast<uint16_t*>(ws + L.dec_off[k]);
+    int32_t d = L.decs[k];
+    int from = -1;
+    for (int j = (int)k - 1; j >= 0; --j)
+      if (d % L.decs[j] == 0) {
+        from = j;
+        break;
+      }
+    StageTimer tm(SDD_STAGE_DECIMATE, s);
+    if (from < 0) {
+      SDD_HIP_TRY(launch_decimate(src, 1, src_pitch, p->nchan, d, dbuf[k], L.dec_pitch[k],
+                                  L.dec_len[k], s));
+    } else {
+      SDD_HIP_TRY(launch_decimate(dbuf[from], 2, L.dec_pitch[from], p->nchan,
+                                  d / L.decs[from], dbuf[k], L.dec_pitch[k], L.dec_len[k], s));
+    }
+  }
+  for (size_t r = 0; r < p->ranges.size(); ++r) {
+    const Range& R = p->ranges[r];
+    DedispArgs a{};
+    if (R.dec == 1) {
+      a.x = src;
+      a.elem_bytes = 1;
+      a.x_pitch = src_pitch;
+      a.x_len = nsamp_in;
+    } else {
+      size_t k = std::find(L.decs.begin(), L.decs.end(), R.dec) - L.decs.begin();
+      a.x = dbuf[k];
+      a.elem_bytes = 2;
+      a.x_pitch = L.dec_pitch[k];
+      a.x_len = L.dec_len[k];
+    }
+    a.nchan = p->nchan;
+    a.delays = p->d_delays[r];
+    a.ndm = R.ndm();
+    a.plane = planes[r];
+    a.plane_pitch = pitch[r];
+    a.cols = cg.g.plane_cols[r];
+    a.max_val = 255 * R.dec;
+    a.tile = R.tile;
+    a.span = 0;
+    if (a.cols + R.max_delay > a.x_len)
+      SDD_FAIL(SDD_EINVAL, "internal: range %zu input too short", r);
+    StageTimer tm(SDD_STAGE_DEDISPERSE, s);
+    SDD_HIP_TRY(launch_dedisperse(a, s));
+  }
+  return SDD_OK;
+}
+
+sdd_status run_search(const sdd_plan* p, const CallGeom& cg, const uint32_t* const* planes,
+                      const int64_t* pitch, sdd_dm_best* best, sdd_dm_stats* stats,
+                      sdd_candidate* cands, int32_t cap, int32_t* ncand, uint8_t* ws,
+                      hipStream_t s) {
+  SearchArgs a{};
+  a.nranges = (int32_t)p->ranges.size();
+  a.ndm_total = p->ndm_total;
+  a.nwidths = (int32_t)p->widths.size();
+  a.w_max = p->w_max;
+  for (int32_t k = 0; k < a.nwidths; ++k) a.widths[k] = p->widths[k];
+  a.cand_block = p->cand_block;
+  a.threshold = p->threshold;
+  a.cap = cap;
+  a.max_cells = 0;
+  for (int32_t r = 0; r < a.nranges; ++r) {
+    const Range& R = p->ranges[r];
+    a.r[r].plane = planes[r];
+    a.r[r].pitch = pitch[r];
+    a.r[r].n_owned = cg.g.n_owned_r[r];
+    a.r[r].ndm = R.ndm();
+    a.r[r].dm_offset = R.dm_offset;
+    a.r[r].ncells = (int32_t)cg.g.ncells[r];
+    a.r[r].cell_base = cg.cell_base[r];
+    a.max_cells = std::max(a.max_cells, a.r[r].ncells);
+  }
+  a.ws = ws;
+  a.cellres_off = cg.ws.cellres_off;
+  a.moments_off = cg.ws.moments_off;
+  a.cellbest_off = cg.ws.cellbest_off;
+  a.rowcnt_off = cg.ws.rowcnt_off;
+  a.rowoff_off = cg.ws.rowoff_off;
+  a.best = best;
+  a.stats = stats;
+  a.cands = cands;
+  a.ncand = ncand;
+  StageTimer tm(SDD_STAGE_SEARCH, s);
+  SDD_HIP_TRY(launch_search(a, s));
+  return SDD_OK;
+}
+
+}  // namespace
+}  // namespace sdd
+
+using namespace sdd;
+
+extern "C" int32_t sdd_abi_version(void) { return SDD_ABI_VERSION; }
+extern "C" const char* sdd_last_error(void) { return sdd::last_error(); }
+extern "C" const char* sdd_status_string(int32_t s) {
+  switch (s) {
+    case SDD_OK: return "SDD_OK";
+    case SDD_EINVAL: return "SDD_EINVAL";
+    case SDD_ERANGE: return "SDD_ERANGE";
+    case SDD_ENOMEM: return "SDD_ENOMEM";
+    case SDD_EDEVICE: return "SDD_EDEVICE";
+    case SDD_EAGAIN: return "SDD_EAGAIN";
+    case SDD_ESTATE: return "SDD_ESTATE";
+    case SDD_ETIMEDOUT: return "SDD_ETIMEDOUT";
+    default: return "unknown status";
+  }
+}
+
+extern "C" sdd_status sdd_dedisperse(const sdd_plan* p, const uint8_t* d_in, int64_t nsamp_in,
+                                     int64_t in_pitch, uint32_t* const* d_planes,
+                                     const int64_t* plane_pitch, void* d_ws, int64_t ws_bytes,
+                                     void* stream) {
+  clear_error();
+  if (!p) SDD_FAIL(SDD_EINVAL, "null plan");
+  CallGeom cg;
+  sdd_status st = plan_geometry(p, nsamp_in, &cg);
+  if (st != SDD_OK) return st;
+  if ((st = check_input(p, d_in, nsamp_in, in_pitch)) != SDD_OK) return st;
+  if ((st = check_planes(p, cg, (const void* const*)d_planes, plane_pitch)) != SDD_OK) return st;
+  if (ws_bytes < cg.ws.total || (cg.ws.total > 0 && !d_ws))
+    SDD_FAIL(SDD_ENOMEM, "workspace %lld bytes < %lld needed", (long long)ws_bytes,
+             (long long)cg.ws.total);
+  DeviceGuard dg(p->device);
+  if (!dg.ok) SDD_FAIL(SDD_EDEVICE, "cannot select device %d", p->device);
+  if ((st = plan_upload(p)) != SDD_OK) return st;
+  return run_dedisperse(p, cg, d_in, nsamp_in, in_pitch, d_planes, plane_pitch, (uint8_t*)d_ws,
+                        (hipStream_t)stream);
+}
+
+extern "C" sdd_status sdd_search_boxcar(const sdd_plan* p, const uint32_t* const* d_planes,
+                                        const int64_t* plane_pitch, int64_t nsamp_in,
+                                        sdd_dm_best* d_best, sdd_dm_stats* d_stats,
+                                        sdd_candidate* d_cands, int32_t cap, int32_t* d_ncand,
+                                        void* d_ws, int64_t ws_bytes, void* stream) {
+  clear_error();
+  if (!p) SDD_FAIL(SDD_EINVAL, "null plan");
+  if (p->widths.empty()) SDD_FAIL(SDD_EINVAL, "plan has no boxcar widths");
+  if (!d_best || !d_ncand || cap < 0 || (cap > 0 && !d_cands))
+    SDD_FAIL(SDD_EINVAL, "null best/ncand, or null candidates with cap > 0");
+  CallGeom cg;
+  sdd_status st = plan_geometry(p, nsamp_in, &cg);
+  if (st != SDD_OK) return st;
+  if ((st = check_planes(p, cg, (const void* const*)d_planes, plane_pitch)) != SDD_OK) return st;
+  if (ws_bytes < cg.ws.total || !d_ws)
+    SDD_FAIL(SDD_ENOMEM, "workspace %lld bytes < %lld needed", (long long)ws_bytes,
+             (long long)cg.ws.total);
+  DeviceGuard dg(p->device);
+  if (!dg.ok) SDD_FAIL(SDD_EDEVICE, "cannot select device %d", p->device);
+  if ((st = plan_upload(p)) != SDD_OK) return st;
+  return run_search(p, cg, d_planes, plane_pitch, d_best, d_stats, d_cands, cap, d_ncand,
+                    (uint8_t*)d_ws, (hipStream_t)stream);
+}
+
+extern "C" sdd_status sdd_dedisperse_search(const sdd_plan* p, const uint8_t* d_in,
+                                            int64_t nsamp_in, int64_t in_pitch,
+                                            uint32_t* const* d_planes,
+                                            const int64_t* plane_pitch, sdd_dm_best* d_best,
+                                            sdd_dm_stats* d_stats, sdd_candidate* d_cands,
+                                            int32_t cap, int32_t* d_ncand, void* d_ws,
+                                            int64_t ws_bytes, void* stream) {
+  clear_error();
+  if (!p) SDD_FAIL(SDD_EINVAL, "null plan");
+  if (p->widths.empty()) SDD_FAIL(SDD_EINVAL, "plan has no boxcar widths");
+  if (!d_best || !d_ncand || cap < 0 || (cap > 0 && !d_cands))
+    SDD_FAIL(SDD_EINVAL, "null best/ncand, or null candidates with cap > 0");
+  CallGeom cg;
+  sdd_status st = plan_geometry(p, nsamp_in, &cg);
+  if (st != SDD_OK) return st;
+  if ((st = check_input(p, d_in, nsamp_in, in_pitch)) != SDD_OK) return st;
+  uint32_t* own[SDD_MAX_RANGES];
+  int64_t own_pitch[SDD_MAX_RANGES];
+  const bool lib_planes = (d_planes == nullptr);
+  const int64_t need = lib_planes ? cg.ws.total_planes : cg.ws.total;
+  if (ws_bytes < need || !d_ws)
+    SDD_FAIL(SDD_ENOMEM, "workspace %lld bytes < %lld needed", (long long)ws_bytes,
+             (long long)need);
+  if (lib_planes) {
+    for (size_t r = 0; r < p->ranges.size(); ++r) {
+      own[r] = reinterpret_cast<uint32_t*>((uint8_t*)d_ws + cg.ws.plane_off[r]);
+      own_pitch[r] = cg.ws.plane_pitch[r];
+    }
+    d_planes = own;
+    plane_pitch = own_pitch;
+  } else if ((st = check_planes(p, cg, (const void* const*)d_planes, plane_pitch)) != SDD_OK) {
+    return st;
+  }
+  DeviceGuard dg(p->device);
+  if (!dg.ok) SDD_FAIL(SDD_EDEVICE, "cannot select device %d", p->device);
+  if ((st = plan_upload(p)) != SDD_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  st = run_dedisperse(p, cg, d_in, nsamp_in, in_pitch, d_planes, plane_pitch, (uint8_t*)d_ws, s);
+  if (st != SDD_OK) return st;
+  return run_search(p, cg, (const uint32_t* const*)d_planes, plane_pitch, d_best, d_stats,
+                    d_cands, cap, d_ncand, (uint8_t*)d_ws, s);
+}

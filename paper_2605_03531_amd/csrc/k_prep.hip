@@ -1,0 +1,102 @@
+// Input preparation kernels: corner turn of spectra-ordered input into
+// channel rows, and exact time decimation (sums of consecutive samples,
+// the downsampling of Section 3.2 applied before dedispersion).
+#include "sdd_internal.h"
+
+namespace sdd {
+namespace {
+
+constexpr int kCtChan = 64;    // channels per corner-turn tile
+constexpr int kCtTime = 256;   // samples per corner-turn tile
+constexpr int kCtPad = 4;
+
+// in: byte (t, c) at in[t * in_pitch + c]; out: byte (c, t) at out[c * out_pitch + t].
+// One workgroup turns a 256-sample x 64-channel tile through LDS: reads are
+// rows of 64 channel bytes per spectrum, writes are rows of 256 sample bytes
+// per channel (one full wavefront of dwords).
+__global__ __launch_bounds__(256) void k_corner_turn(const uint8_t* __restrict__ in, int64_t nsamp,
+                                                     int64_t in_pitch, int32_t nchan,
+                                                     uint8_t* __restrict__ out, int64_t out_pitch,
+                                                     int dword_in, int dword_out) {
+  __shared__ __attribute__((aligned(16))) uint8_t tile[kCtChan][kCtTime + kCtPad];
+  const int tid = threadIdx.x;
+  const int32_t c0 = blockIdx.y * kCtChan;
+  const int64_t t0 = (int64_t)blockIdx.x * kCtTime;
+  const int cc = (tid & 15) * 4;
+#pragma unroll 4
+  for (int k = 0; k < kCtTime / 16; ++k) {
+    const int r = (tid >> 4) + 16 * k;
+    const int64_t t = t0 + r;
+    uint32_t v = 0;
+    if (t < nsamp) {
+      const uint8_t* src = in + t * in_pitch + c0 + cc;
+      if (dword_in && c0 + cc + 3 < nchan) {
+        v = *reinterpret_cast<const uint32_t*>(src);
+      } else {
+        for (int b = 0; b < 4; ++b)
+          if (c0 + cc + b < nchan) v |= (uint32_t)src[b] << (8 * b);
+      }
+    }
+    tile[cc + 0][r] = (uint8_t)(v);
+    tile[cc + 1][r] = (uint8_t)(v >> 8);
+    tile[cc + 2][r] = (uint8_t)(v >> 16);
+    tile[cc + 3][r] = (uint8_t)(v >> 24);
+  }
+  __syncthreads();
+  const int tt = (tid & 63) * 4;
+#pragma unroll 4
+  for (int k = 0; k < kCtChan / 4; ++k) {
+    const int cr = (tid >> 6) + 4 * k;
+    const int32_t c = c0 + cr;
+    const int64_t t = t0 + tt;
+    if (c >= nchan || t >= nsamp) continue;
+    uint8_t* dst = out + (int64_t)c * out_pitch + t;
+    if (dword_out && t + 3 < nsamp) {
+      *reinterpret_cast<uint32_t*>(dst) = *reinterpret_cast<const uint32_t*>(&tile[cr][tt]);
+    } else {
+      for (int b = 0; b < 4 && t + b < nsamp; ++b) dst[b] = tile[cr][tt + b];
+    }
+  }
+}
+
+template <typename Tin>
+__global__ __launch_bounds__(256) void k_decimate(const Tin* __restrict__ in, int64_t in_pitch,
+                                                  int32_t nchan, int32_t factor,
+                                                  uint16_t* __restrict__ out, int64_t out_pitch,
+                                                  int64_t out_len) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= out_len) return;
+  for (int32_t c = blockIdx.y; c < nchan; c += gridDim.y) {
+    const Tin* src = in + (int64_t)c * in_pitch + j * factor;
+    uint32_t s = 0;
+    for (int k = 0; k < factor; ++k) s += src[k];
+    out[(int64_t)c * out_pitch + j] = (uint16_t)s;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_corner_turn(const uint8_t* in, int64_t nsamp, int64_t in_pitch, int32_t nchan,
+                              uint8_t* out, int64_t out_pitch, hipStream_t s) {
+  const int dword_in = ((uintptr_t)in % 4 == 0) && (in_pitch % 4 == 0);
+  const int dword_out = ((uintptr_t)out % 4 == 0) && (out_pitch % 4 == 0);
+  dim3 grid((unsigned)((nsamp + kCtTime - 1) / kCtTime), (unsigned)((nchan + kCtChan - 1) / kCtChan));
+  hipLaunchKernelGGL(k_corner_turn, grid, dim3(256), 0, s, in, nsamp, in_pitch, nchan, out,
+                     out_pitch, dword_in, dword_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_decimate(const void* in, int in_bytes, int64_t in_pitch, int32_t nchan,
+                           int32_t factor, uint16_t* out, int64_t out_pitch, int64_t out_len,
+                           hipStream_t s) {
+  dim3 grid((unsigned)((out_len + 255) / 256), (unsigned)(nchan < 1024 ? nchan : 1024));
+  if (in_bytes == 1)
+    hipLaunchKernelGGL(k_decimate<uint8_t>, grid, dim3(256), 0, s, (const uint8_t*)in, in_pitch,
+                       nchan, factor, out, out_pitch, out_len);
+  else
+    hipLaunchKernelGGL(k_decimate<uint16_t>, grid, dim3(256), 0, s, (const uint16_t*)in,
+                       in_pitch, nchan, factor, out, out_pitch, out_len);
+  return hipGetLastError();
+}
+
+}  // namespace sdd

@@ -1,0 +1,367 @@
+// Single-pulse search by time-domain boxcar filtering (Section 2.1) over the
+// dedispersed DM-time planes:
+//   k_cells    per (trial, cell of owned starts): wrap-around uint32 prefix
+//              sums in LDS give B_w[j] = P[j+w] - P[j] exactly; the maximum
+//              and first argmax per width; exact uint64 S1/S2 of the owned
+//              samples, accumulated per trial with integer atomics.
+//   k_rows     per trial: FP64 mean/sigma from the exact moments, S/N of each
+//              cell's per-width maxima, the cell's best, the trial's best and
+//              its candidate count (S/N > threshold).
+//   k_scan     exclusive scan of the per-trial counts (one workgroup).
+//   k_compact  per trial: writes its candidates in sample order at its offset.
+// Every step is deterministic: integer sums are order-free and every
+// selection has a total tie order.
+#include <cmath>
+
+#include "sdd_internal.h"
+
+namespace sdd {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kSub = 1024;  // owned starts per LDS sub-segment
+
+struct CellRes {
+  uint32_t b;
+  int32_t j;
+};
+struct CellBest {
+  double snr;
+  int32_t j;
+  uint32_t wf;  // width | (candidate << 31)
+};
+struct Moments {
+  unsigned long long s1, s2;
+};
+
+__device__ inline int find_range(const SearchArgs& a, int32_t g) {
+  int r = 0;
+  for (int k = 1; k < a.nranges; ++k)
+    if (g >= a.r[k].dm_offset) r = k;
+  return r;
+}
+
+__device__ inline unsigned long long wave_max_u64(unsigned long long v) {
+  for (int o = 32; o > 0; o >>= 1) {
+    unsigned long long t = __shfl_xor(v, o, 64);
+    v = t > v ? t : v;
+  }
+  return v;
+}
+
+__device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Exclusive scan over the workgroup (kThreads threads); tmp holds one entry
+// per wavefront. Contains two barriers.
+template <typename T>
+__device__ inline T block_exclusive_scan(T v, T* tmp, T* total) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  T inc = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    T t = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += t;
+  }
+  if (lane == 63) tmp[wid] = inc;
+  __syncthreads();
+  T off = 0, tot = 0;
+  for (int w = 0; w < kThreads / 64; ++w) {
+    T t = tmp[w];
+    if (w < wid) off += t;
+    tot += t;
+  }
+  __syncthreads();
+  *total = tot;
+  return off + inc - v;
+}
+
+__global__ __launch_bounds__(256) void k_zero_u64(unsigned long long* p, int64_t n) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) p[k] = 0ull;
+}
+
+__global__ __launch_bounds__(kThreads) void k_cells(SearchArgs a) {
+  extern __shared__ uint32_t sm[];  // kSub + w_max entries
+  __shared__ unsigned long long red[kThreads / 64];
+  __shared__ unsigned long long run_best[SDD_MAX_WIDTHS];
+  __shared__ uint32_t scan_tmp[kThreads / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int32_t g = blockIdx.x;
+  const int r = find_range(a, g);
+  const SearchRange& R = a.r[r];
+  const int32_t i = g - R.dm_offset;
+  const uint32_t* row = R.plane + (int64_t)i * R.pitch;
+  Moments* mom = reinterpret_cast<Moments*>(a.ws + a.moments_off);
+  CellRes* cres = reinterpret_cast<CellRes*>(a.ws + a.cellres_off);
+  unsigned long long s1 = 0, s2 = 0;
+  for (int32_t cell = blockIdx.y; cell < R.ncells; cell += gridDim.y) {
+    const int64_t jb = (int64_t)cell * a.cand_block;
+    const int64_t je = min(jb + (int64_t)a.cand_block, R.n_owned);
+    if (tid < a.nwidths) run_best[tid] = 0ull;
+    for (int64_t s0 = jb; s0 < je; s0 += kSub) {
+      const int cnt = (int)min((int64_t)kSub, je - s0);
+      const int len = cnt + a.w_max - 1;
+      __syncthreads();  // previous users of sm / run_best init
+      for (int k = tid; k < len; k += kThreads) sm[k] = row[s0 + k];
+      __syncthreads();
+      for (int k = tid; k < cnt; k += kThreads) {
+        unsigned long long v = sm[k];
+        s1 += v;
+        s2 += v * v;
+      }
+      // in-place exclusive prefix over sm[0, len), sm[len] = total (mod 2^32)
+      const int per = (len + kThreads - 1) / kThreads;
+      const int k0 = min(tid * per, len), k1 = min(k0 + per, len);
+      uint32_t part = 0;
+      for (int k = k0; k < k1; ++k) part += sm[k];
+      uint32_t total;
+      uint32_t off = block_exclusive_scan<uint32_t>(part, scan_tmp, &total);
+      for (int k = k0; k < k1; ++k) {
+        uint32_t v = sm[k];
+        sm[k] = off;
+        off += v;
+      }
+      if (tid == 0) sm[len] = total;
+      __syncthreads();
+      for (int k = 0; k < a.nwidths; ++k) {
+        const int w = a.widths[k];
+        unsigned long long key = 0ull;
+        for (int q = tid; q < cnt; q += kThreads) {
+          const uint32_t b = sm[q + w] - sm[q];
+          const uint32_t jr = (uint32_t)(s0 - jb + q);
+          const unsigned long long kk = ((unsigned long long)b << 32) | (uint32_t)(~jr);
+          key = kk > key ? kk : key;
+        }
+        key = wave_max_u64(key);
+        if (lane == 0) red[wid] = key;
+        __syncthreads();
+        if (tid == 0) {
+          unsigned long long m = run_best[k];
+          for (int w2 = 0; w2 < kThreads / 64; ++w2) m = red[w2] > m ? red[w2] : m;
+          run_best[k] = m;
+        }
+        __syncthreads();
+      }
+    }
+    __syncthreads();
+    if (tid < a.nwidths) {
+      const unsigned long long m = run_best[tid];
+      CellRes c;
+      c.b = (uint32_t)(m >> 32);
+      c.j = (int32_t)(jb + (int64_t)(~(uint32_t)m));
+      cres[(R.cell_base + (int64_t)i * R.ncells + cell) * a.nwidths + tid] = c;
+    }
+  }
+  // exact moments of this block's owned samples
+  s1 = wave_sum_u64(s1);
+  s2 = wave_sum_u64(s2);
+  __shared__ unsigned long long m1[kThreads / 64], m2[kThreads / 64];
+  if (lane == 0) {
+    m1[wid] = s1;
+    m2[wid] = s2;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    unsigned long long t1 = 0, t2 = 0;
+    for (int w2 = 0; w2 < kThreads / 64; ++w2) {
+      t1 += m1[w2];
+      t2 += m2[w2];
+    }
+    atomicAdd(&mom[g].s1, t1);
+    atomicAdd(&mom[g].s2, t2);
+  }
+}
+
+// true if (s, j, w) comes before (s2, j2, w2): higher S/N, then smaller j,
+// then smaller w.
+__device__ inline bool better(double s, int64_t j, int w, double s2, int64_t j2, int w2) {
+  if (s != s2) return s > s2;
+  if (j != j2) return j < j2;
+  return w < w2;
+}
+
+__global__ __launch_bounds__(kThreads) void k_rows(SearchArgs a) {
+  __shared__ double rs[kThreads];
+  __shared__ int64_t rj[kThreads];
+  __shared__ int rw[kThreads];
+  __shared__ int rc[kThreads];
+  const int tid = threadIdx.x;
+  const int32_t g = blockIdx.x;
+  const int r = find_range(a, g);
+  const SearchRange& R = a.r[r];
+  const int32_t i = g - R.dm_offset;
+  const Moments m = reinterpret_cast<const Moments*>(a.ws + a.moments_off)[g];
+  const CellRes* cres = reinterpret_cast<const CellRes*>(a.ws + a.cellres_off);
+  CellBest* cbest = reinterpret_cast<CellBest*>(a.ws + a.cellbest_off);
+  const uint64_t n = (uint64_t)R.n_owned;
+  // D = n*S2 - S1^2 exactly (128-bit), sigma = sqrt(D)/n
+  const uint64_t p_lo = n * m.s2, p_hi = __umul64hi(n, m.s2);
+  const uint64_t q_lo = m.s1 * m.s1, q_hi = __umul64hi(m.s1, m.s1);
+  const uint64_t d_lo = p_lo - q_lo;
+  const uint64_t d_hi = p_hi - q_hi - (p_lo < q_lo ? 1ull : 0ull);
+  const double mu = (double)m.s1 / (double)n;
+  double sigma = 0.0;
+  if (d_hi != 0 || d_lo != 0) {
+    const double dd = (double)d_hi * 18446744073709551616.0 + (double)d_lo;
+    sigma = sqrt(dd) / (double)n;
+  }
+  if (tid == 0 && a.stats) {
+    sdd_dm_stats st;
+    st.n = (int64_t)n;
+    st.s1 = m.s1;
+    st.s2 = m.s2;
+    st.mean = mu;
+    st.std = sigma;
+    a.stats[g] = st;
+  }
+  double bs = -INFINITY;
+  int64_t bj = 0;
+  int bw = 0;
+  int cnt = 0;
+  const double thr = (double)a.threshold;
+  for (int32_t c = tid; c < R.ncells; c += kThreads) {
+    const int64_t cidx = R.cell_base + (int64_t)i * R.ncells + c;
+    const CellRes* cr = cres + cidx * a.nwidths;
+    double cs;
+    int64_t cj;
+    int cw;
+    if (sigma == 0.0) {
+      cs = 0.0;
+      cj = (int64_t)c * a.cand_block;
+      cw = a.widths[0];
+    } else {
+      cs = -INFINITY;
+      cj = 0;
+      cw = 0;
+      for (int k = 0; k < a.nwidths; ++k) {
+        const int w = a.widths[k];
+        const double s = ((double)cr[k].b - (double)w * mu) / (sigma * sqrt((double)w));
+        if (better(s, cr[k].j, w, cs, cj, cw)) {
+          cs = s;
+          cj = cr[k].j;
+          cw = w;
+        }
+      }
+    }
+    const bool flag = sigma > 0.0 && cs > thr;
+    CellBest cb;
+    cb.snr = cs;
+    cb.j = (int32_t)cj;
+    cb.wf = (uint32_t)cw | (flag ? 0x80000000u : 0u);
+    cbest[cidx] = cb;
+    cnt += flag ? 1 : 0;
+    if (better(cs, cj, cw, bs, bj, bw)) {
+      bs = cs;
+      bj = cj;
+      bw = cw;
+    }
+  }
+  rs[tid] = bs;
+  rj[tid] = bj;
+  rw[tid] = bw;
+  rc[tid] = cnt;
+  __syncthreads();
+  for (int h = kThreads / 2; h > 0; h >>= 1) {
+    if (tid < h) {
+      if (better(rs[tid + h], rj[tid + h], rw[tid + h], rs[tid], rj[tid], rw[tid])) {
+        rs[tid] = rs[tid + h];
+        rj[tid] = rj[tid + h];
+        rw[tid] = rw[tid + h];
+      }
+      rc[tid] += rc[tid + h];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    sdd_dm_best b;
+    b.snr = (float)rs[0];
+    b.width = rw[0];
+    b.sample = rj[0];
+    a.best[g] = b;
+    reinterpret_cast<int32_t*>(a.ws + a.rowcnt_off)[g] = rc[0];
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_scan(SearchArgs a) {
+  __shared__ int32_t tmp[16];
+  const int32_t* cnt = reinterpret_cast<const int32_t*>(a.ws + a.rowcnt_off);
+  int32_t* off = reinterpret_cast<int32_t*>(a.ws + a.rowoff_off);
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  int32_t carry = 0;
+  for (int32_t base = 0; base < a.ndm_total; base += 1024) {
+    const int32_t g = base + tid;
+    const int32_t v = g < a.ndm_total ? cnt[g] : 0;
+    int32_t inc = v;
+    for (int o = 1; o < 64; o <<= 1) {
+      int32_t t = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += t;
+    }
+    if (lane == 63) tmp[wid] = inc;
+    __syncthreads();
+    int32_t woff = 0, tot = 0;
+    for (int w = 0; w < 16; ++w) {
+      if (w < wid) woff += tmp[w];
+      tot += tmp[w];
+    }
+    if (g < a.ndm_total) off[g] = carry + woff + inc - v;
+    carry += tot;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    off[a.ndm_total] = carry;
+    *a.ncand = carry;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_compact(SearchArgs a) {
+  __shared__ int32_t tmp[kThreads / 64];
+  const int tid = threadIdx.x;
+  const int32_t g = blockIdx.x;
+  const int r = find_range(a, g);
+  const SearchRange& R = a.r[r];
+  const int32_t i = g - R.dm_offset;
+  const CellBest* cbest = reinterpret_cast<const CellBest*>(a.ws + a.cellbest_off);
+  int32_t base = reinterpret_cast<const int32_t*>(a.ws + a.rowoff_off)[g];
+  for (int32_t c0 = 0; c0 < R.ncells; c0 += kThreads) {
+    const int32_t c = c0 + tid;
+    CellBest cb{};
+    bool flag = false;
+    if (c < R.ncells) {
+      cb = cbest[R.cell_base + (int64_t)i * R.ncells + c];
+      flag = (cb.wf & 0x80000000u) != 0;
+    }
+    int32_t total;
+    const int32_t ex = block_exclusive_scan<int32_t>(flag ? 1 : 0, tmp, &total);
+    const int32_t at = base + ex;
+    if (flag && at < a.cap) {
+      sdd_candidate o;
+      o.range = r;
+      o.dm_index = i;
+      o.sample = cb.j;
+      o.width = (int32_t)(cb.wf & 0x7fffffffu);
+      o.snr = (float)cb.snr;
+      a.cands[at] = o;
+    }
+    base += total;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_search(const SearchArgs& a, hipStream_t s) {
+  if (a.ndm_total <= 0) return hipSuccess;
+  const int64_t nm = 2 * (int64_t)a.ndm_total;
+  hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)((nm + 255) / 256)), dim3(256), 0, s,
+                     reinterpret_cast<unsigned long long*>(a.ws + a.moments_off), nm);
+  const unsigned gy = (unsigned)(a.max_cells < 1 ? 1 : (a.max_cells > 65535 ? 65535 : a.max_cells));
+  const size_t lds = (size_t)(kSub + a.w_max) * sizeof(uint32_t);
+  hipLaunchKernelGGL(k_cells, dim3((unsigned)a.ndm_total, gy), dim3(kThreads), lds, s, a);
+  hipLaunchKernelGGL(k_rows, dim3((unsigned)a.ndm_total), dim3(kThreads), 0, s, a);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, a);
+  hipLaunchKernelGGL(k_compact, dim3((unsigned)a.ndm_total), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace sdd

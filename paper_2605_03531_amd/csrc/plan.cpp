@@ -1,0 +1,396 @@
+// Host side of the plan: descriptor validation, the FP64 delay tables
+// (Chapter 1, Eq. (1)), the exactness guards, per-call geometry and the
+// workspace layout. Nothing here launches a kernel; only plan_upload touches
+// the GPU (on first use by a compute call).
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "sdd_internal.h"
+
+namespace sdd {
+
+namespace {
+thread_local char g_err[1024] = {0};
+
+int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+// Delay of every channel at one trial DM, in samples of dec * t_samp, rounded
+// half up. Written as ((K * DM) * diff) / den so it rounds exactly as the
+// documented left-to-right FP64 evaluation; this file is compiled without
+// floating-point contraction.
+sdd_status build_delays(const std::vector<double>& freqs, double t_samp, Range& r) {
+  const double ftop = *std::max_element(freqs.begin(), freqs.end());
+  const double inv_top = 1.0 / (ftop * ftop);
+  std::vector<double> diff(freqs.size());
+  for (size_t c = 0; c < freqs.size(); ++c) diff[c] = 1.0 / (freqs[c] * freqs[c]) - inv_top;
+  const double den = (double)r.dec * t_samp;
+  const size_t nchan = freqs.size();
+  r.delays.assign(r.dms.size() * nchan, 0);
+  r.max_delay = 0;
+  for (size_t i = 0; i < r.dms.size(); ++i) {
+    for (size_t c = 0; c < nchan; ++c) {
+      double v = kDispersionConstant * r.dms[i] * diff[c] / den;
+      double d = std::floor(v + 0.5);
+      if (!(d >= 0.0) || d > 1.0e9)
+        SDD_FAIL(SDD_ERANGE, "delay %g samples at DM %g channel %zu is out of range", d,
+                 r.dms[i], c);
+      int32_t di = (int32_t)d;
+      r.delays[i * nchan + c] = di;
+      r.max_delay = std::max(r.max_delay, di);
+    }
+  }
+  return SDD_OK;
+}
+}  // namespace
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+void clear_error() { g_err[0] = 0; }
+const char* last_error() { return g_err; }
+
+const std::vector<sdd_tile>& tile_menu() {
+  static const std::vector<sdd_tile> menu = {
+      {0, 0, 0, 0, 0, 0},
+  };
+  return menu;
+}
+
+bool tile_in_menu(const sdd_tile& t) {
+  for (const auto& m : tile_menu())
+    if (std::memcmp(&m, &t, sizeof(sdd_tile)) == 0) return true;
+  return false;
+}
+
+int32_t range_span(const sdd_plan* p, int32_t r, int32_t dm_tile) {
+  const Range& R = p->ranges[r];
+  const int32_t ndm = R.ndm(), C = p->nchan;
+  int32_t span = 0;
+  for (int32_t i0 = 0; i0 < ndm; i0 += dm_tile) {
+    int32_t i1 = std::min(ndm, i0 + dm_tile) - 1;
+    for (int32_t c = 0; c < C; ++c)
+      span = std::max(span, R.delays[(size_t)i1 * C + c] - R.delays[(size_t)i0 * C + c]);
+  }
+  return span;
+}
+
+sdd_status check_tile_fits(const sdd_plan* p, int32_t r, const sdd_tile& t) {
+  (void)p;
+  (void)r;
+  if (!tile_in_menu(t)) SDD_FAIL(SDD_EINVAL, "tile shape not in the built menu");
+  return SDD_OK;
+}
+
+sdd_tile default_tile(const sdd_plan* p, int32_t r) {
+  (void)p;
+  (void)r;
+  return tile_menu()[0];
+}
+
+sdd_status plan_geometry(const sdd_plan* p, int64_t nsamp_in, CallGeom* out) {
+  CallGeom cg;
+  sdd_geometry& g = cg.g;
+  std::memset(&g, 0, sizeof(g));
+  g.nsamp_in = nsamp_in;
+  g.overlap = p->overlap;
+  g.n_owned = nsamp_in - p->overlap;
+  if (nsamp_in <= 0 || g.n_owned < p->dec_max)
+    SDD_FAIL(SDD_EINVAL,
+             "nsamp_in %lld too short: needs at least overlap %lld + %d samples",
+             (long long)nsamp_in, (long long)p->overlap, p->dec_max);
+  const int32_t nw = (int32_t)p->widths.size();
+  WsLayout& ws = cg.ws;
+  int64_t off = 0;
+  auto take = [&](int64_t bytes) {
+    int64_t o = off;
+    off = round_up(off + bytes, 256);
+    return o;
+  };
+  if (p->layout == SDD_TIME_MAJOR) {
+    ws.ct_pitch = round_up(nsamp_in, 256);
+    ws.ct_off = take(ws.ct_pitch * p->nchan);
+  }
+  for (const auto& R : p->ranges)
+    if (R.dec > 1 && std::find(ws.decs.begin(), ws.decs.end(), R.dec) == ws.decs.end())
+      ws.decs.push_back(R.dec);
+  std::sort(ws.decs.begin(), ws.decs.end());
+  for (int32_t d : ws.decs) {
+    int64_t len = nsamp_in / d;
+    int64_t pitch = round_up(len, 128);
+    ws.dec_len.push_back(len);
+    ws.dec_pitch.push_back(pitch);
+    ws.dec_off.push_back(take(pitch * 2 * p->nchan));
+  }
+  int64_t cells_total = 0;
+  for (size_t r = 0; r < p->ranges.size(); ++r) {
+    const Range& R = p->ranges[r];
+    int64_t nr = g.n_owned / R.dec;
+    g.n_owned_r[r] = nr;
+    g.plane_cols[r] = nr + p->w_max - 1;
+    g.ncells[r] = p->cells_for(nr);
+    cg.cell_base[r] = cells_total;
+    cells_total += g.ncells[r] * R.ndm();
+    if (nw > 0) {
+      // S2 = sum y^2 < 2^64 with y <= nchan * 255 * dec
+      long double ymax = (long double)p->nchan * 255.0L * R.dec;
+      if ((long double)nr * ymax * ymax >= 18446744073709551615.0L)
+        SDD_FAIL(SDD_ERANGE, "range %zu: %lld owned samples could overflow the 64-bit S2 sum",
+                 r, (long long)nr);
+    }
+  }
+  ws.search_cells = cells_total;
+  if (nw > 0) {
+    ws.cellres_off = take(cells_total * nw * 8);
+    ws.moments_off = take((int64_t)p->ndm_total * 16);
+    ws.cellbest_off = take(cells_total * 16);
+    ws.rowcnt_off = take((int64_t)p->ndm_total * 4);
+    ws.rowoff_off = take(((int64_t)p->ndm_total + 1) * 4);
+  }
+  ws.total = off;
+  for (size_t r = 0; r < p->ranges.size(); ++r) {
+    ws.plane_pitch[r] = round_up(g.plane_cols[r], 64);
+    ws.plane_off[r] = take(ws.plane_pitch[r] * 4 * p->ranges[r].ndm());
+  }
+  ws.total_planes = off;
+  g.workspace_bytes = ws.total;
+  g.workspace_bytes_planes = ws.total_planes;
+  *out = cg;
+  return SDD_OK;
+}
+
+sdd_status plan_upload(const sdd_plan* p) {
+  std::lock_guard<std::mutex> lk(p->mu);
+  if (p->uploaded_device == p->device) return SDD_OK;
+  const int32_t C = p->nchan;
+  p->d_delays.assign(p->ranges.size(), nullptr);
+  for (size_t r = 0; r < p->ranges.size(); ++r) {
+    const Range& R = p->ranges[r];
+    const int32_t ndm = R.ndm();
+    std::vector<int32_t> cm((size_t)ndm * C);
+    for (int32_t i = 0; i < ndm; ++i)
+      for (int32_t c = 0; c < C; ++c) cm[(size_t)c * ndm + i] = R.delays[(size_t)i * C + c];
+    int32_t* d = nullptr;
+    SDD_HIP_TRY(hipMalloc(&d, cm.size() * sizeof(int32_t)));
+    p->d_delays[r] = d;
+    SDD_HIP_TRY(hipMemcpy(d, cm.data(), cm.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  }
+  if (!p->widths.empty()) {
+    SDD_HIP_TRY(hipMalloc(&p->d_widths, p->widths.size() * sizeof(int32_t)));
+    SDD_HIP_TRY(hipMemcpy(p->d_widths, p->widths.data(), p->widths.size() * sizeof(int32_t),
+                          hipMemcpyHostToDevice));
+  }
+  p->uploaded_device = p->device;
+  return SDD_OK;
+}
+
+}  // namespace sdd
+
+using namespace sdd;
+
+static bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+extern "C" sdd_status sdd_plan_create(const sdd_plan_desc* d, sdd_plan** out) {
+  clear_error();
+  if (!d || !out) SDD_FAIL(SDD_EINVAL, "null descriptor or output pointer");
+  *out = nullptr;
+  if (!d->freqs_mhz || d->nchan < 1) SDD_FAIL(SDD_EINVAL, "need nchan >= 1 frequencies");
+  if (!finite_pos(d->t_samp_s)) SDD_FAIL(SDD_EINVAL, "t_samp must be finite and > 0");
+  if ((d->dm_list != nullptr) == (d->ranges != nullptr))
+    SDD_FAIL(SDD_EINVAL, "give exactly one of dm_list and ranges");
+  if (d->layout != SDD_CHAN_MAJOR && d->layout != SDD_TIME_MAJOR)
+    SDD_FAIL(SDD_EINVAL, "unknown layout %d", d->layout);
+  if (d->device < 0) SDD_FAIL(SDD_EINVAL, "bad device %d", d->device);
+  if (d->nwidths < 0 || d->nwidths > SDD_MAX_WIDTHS)
+    SDD_FAIL(SDD_EINVAL, "nwidths must be in [0, %d]", SDD_MAX_WIDTHS);
+  if (d->nwidths > 0 && !d->widths) SDD_FAIL(SDD_EINVAL, "null widths");
+  if (d->cand_block < 0) SDD_FAIL(SDD_EINVAL, "cand_block must be >= 1 (0 = 1024)");
+  if (!std::isfinite(d->threshold)) SDD_FAIL(SDD_EINVAL, "threshold must be finite");
+
+  sdd_plan* p = new sdd_plan();
+  p->nchan = d->nchan;
+  p->layout = d->layout;
+  p->device = d->device;
+  p->cand_block = d->cand_block == 0 ? 1024 : d->cand_block;
+  p->threshold = d->threshold;
+  p->t_samp = d->t_samp_s;
+  p->freqs.assign(d->freqs_mhz, d->freqs_mhz + d->nchan);
+  for (double f : p->freqs)
+    if (!finite_pos(f)) {
+      delete p;
+      SDD_FAIL(SDD_EINVAL, "frequencies must be finite and > 0");
+    }
+  for (int32_t k = 0; k < d->nwidths; ++k) {
+    int32_t w = d->widths[k];
+    if (w < 1 || (k > 0 && w <= d->widths[k - 1])) {
+      delete p;
+      SDD_FAIL(SDD_EINVAL, "widths must be >= 1 and strictly ascending");
+    }
+    p->widths.push_back(w);
+  }
+  p->w_max = p->widths.empty() ? 1 : p->widths.back();
+  if (p->w_max > SDD_MAX_WMAX) {
+    delete p;
+    SDD_FAIL(SDD_EINVAL, "largest width %d exceeds %d", p->w_max, SDD_MAX_WMAX);
+  }
+  if (d->dm_list) {
+    if (d->ndm < 1) {
+      delete p;
+      SDD_FAIL(SDD_EINVAL, "ndm must be >= 1");
+    }
+    Range R;
+    R.dec = 1;
+    R.dms.assign(d->dm_list, d->dm_list + d->ndm);
+    p->ranges.push_back(R);
+  } else {
+    if (d->nranges < 1 || d->nranges > SDD_MAX_RANGES) {
+      delete p;
+      SDD_FAIL(SDD_EINVAL, "nranges must be in [1, %d]", SDD_MAX_RANGES);
+    }
+    for (int32_t r = 0; r < d->nranges; ++r) {
+      const sdd_dm_range& g = d->ranges[r];
+      if (!(g.dm_step > 0.0) || !std::isfinite(g.dm_step) || !std::isfinite(g.dm_lo) ||
+          !std::isfinite(g.dm_hi) || g.decimation < 1) {
+        delete p;
+        SDD_FAIL(SDD_EINVAL, "range %d: need finite lo/hi, step > 0 and decimation >= 1", r);
+      }
+      double cnt = std::floor((g.dm_hi - g.dm_lo) / g.dm_step + 0.5);
+      if (!(cnt >= 1.0) || cnt > 1.0e7) {
+        delete p;
+        SDD_FAIL(SDD_EINVAL, "range %d: trial count %g out of range", r, cnt);
+      }
+      Range R;
+      R.dec = g.decimation;
+      for (int64_t i = 0; i < (int64_t)cnt; ++i) R.dms.push_back(g.dm_lo + (double)i * g.dm_step);
+      p->ranges.push_back(R);
+    }
+  }
+  int32_t off = 0;
+  for (auto& R : p->ranges) {
+    for (double dm : R.dms)
+      if (!(dm >= 0.0) || !std::isfinite(dm)) {
+        delete p;
+        SDD_FAIL(SDD_EINVAL, "trial DMs must be finite and >= 0");
+      }
+    sdd_status st = build_delays(p->freqs, p->t_samp, R);
+    if (st != SDD_OK) {
+      delete p;
+      return st;
+    }
+    R.dm_offset = off;
+    off += R.ndm();
+    p->dec_max = std::max(p->dec_max, R.dec);
+  }
+  p->ndm_total = off;
+  // exact uint32 planes and boxcar sums: nchan * 255 * dec * w_max < 2^32
+  long double bmax = (long double)p->nchan * 255.0L * p->dec_max * p->w_max;
+  if (bmax >= 4294967296.0L) {
+    delete p;
+    SDD_FAIL(SDD_ERANGE, "nchan*255*dec*w_max = %.0Lf does not fit 32 bits", bmax);
+  }
+  int64_t O = 0;
+  for (const auto& R : p->ranges)
+    O = std::max<int64_t>(O, ((int64_t)R.max_delay + p->w_max - 1) * R.dec);
+  p->overlap = O;
+  for (size_t r = 0; r < p->ranges.size(); ++r) p->ranges[r].tile = default_tile(p, (int32_t)r);
+  *out = p;
+  return SDD_OK;
+}
+
+extern "C" sdd_status sdd_plan_destroy(sdd_plan* p) {
+  clear_error();
+  if (!p) return SDD_OK;
+  if (p->uploaded_device >= 0) {
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(p->uploaded_device);
+    for (int32_t* d : p->d_delays) (void)hipFree(d);
+    if (p->d_widths) (void)hipFree(p->d_widths);
+    (void)hipSetDevice(prev);
+  }
+  delete p;
+  return SDD_OK;
+}
+
+extern "C" sdd_status sdd_plan_query(const sdd_plan* p, sdd_plan_info* o) {
+  clear_error();
+  if (!p || !o) SDD_FAIL(SDD_EINVAL, "null argument");
+  std::memset(o, 0, sizeof(*o));
+  o->nchan = p->nchan;
+  o->nranges = (int32_t)p->ranges.size();
+  o->ndm_total = p->ndm_total;
+  o->nwidths = (int32_t)p->widths.size();
+  o->w_max = p->w_max;
+  o->cand_block = p->cand_block;
+  o->layout = p->layout;
+  o->device = p->device;
+  o->overlap = p->overlap;
+  for (size_t r = 0; r < p->ranges.size(); ++r) {
+    o->ndm[r] = p->ranges[r].ndm();
+    o->dm_offset[r] = p->ranges[r].dm_offset;
+    o->decimation[r] = p->ranges[r].dec;
+    o->max_delay[r] = p->ranges[r].max_delay;
+  }
+  return SDD_OK;
+}
+
+extern "C" sdd_status sdd_plan_delays(const sdd_plan* p, int32_t r, int32_t* host_out) {
+  clear_error();
+  if (!p || !host_out) SDD_FAIL(SDD_EINVAL, "null argument");
+  if (r < 0 || r >= (int32_t)p->ranges.size()) SDD_FAIL(SDD_EINVAL, "bad range %d", r);
+  std::memcpy(host_out, p->ranges[r].delays.data(), p->ranges[r].delays.size() * 4);
+  return SDD_OK;
+}
+
+extern "C" sdd_status sdd_plan_dms(const sdd_plan* p, int32_t r, double* host_out) {
+  clear_error();
+  if (!p || !host_out) SDD_FAIL(SDD_EINVAL, "null argument");
+  if (r < 0 || r >= (int32_t)p->ranges.size()) SDD_FAIL(SDD_EINVAL, "bad range %d", r);
+  std::memcpy(host_out, p->ranges[r].dms.data(), p->ranges[r].dms.size() * 8);
+  return SDD_OK;
+}
+
+extern "C" sdd_status sdd_plan_geometry(const sdd_plan* p, int64_t nsamp_in, sdd_geometry* o) {
+  clear_error();
+  if (!p || !o) SDD_FAIL(SDD_EINVAL, "null argument");
+  CallGeom cg;
+  sdd_status st = plan_geometry(p, nsamp_in, &cg);
+  if (st != SDD_OK) return st;
+  *o = cg.g;
+  return SDD_OK;
+}
+
+extern "C" sdd_status sdd_plan_get_tile(const sdd_plan* p, int32_t r, sdd_tile* o) {
+  clear_error();
+  if (!p || !o) SDD_FAIL(SDD_EINVAL, "null argument");
+  if (r < 0 || r >= (int32_t)p->ranges.size()) SDD_FAIL(SDD_EINVAL, "bad range %d", r);
+  *o = p->ranges[r].tile;
+  return SDD_OK;
+}
+
+extern "C" sdd_status sdd_plan_set_tile(sdd_plan* p, int32_t r, const sdd_tile* t) {
+  clear_error();
+  if (!p || !t) SDD_FAIL(SDD_EINVAL, "null argument");
+  if (r < -1 || r >= (int32_t)p->ranges.size()) SDD_FAIL(SDD_EINVAL, "bad range %d", r);
+  int32_t r0 = r < 0 ? 0 : r, r1 = r < 0 ? (int32_t)p->ranges.size() : r + 1;
+  for (int32_t k = r0; k < r1; ++k) {
+    sdd_status st = check_tile_fits(p, k, *t);
+    if (st != SDD_OK) return st;
+  }
+  for (int32_t k = r0; k < r1; ++k) p->ranges[k].tile = *t;
+  return SDD_OK;
+}
+
+extern "C" sdd_status sdd_tile_menu(sdd_tile* host_out, int32_t max, int32_t* n_out) {
+  clear_error();
+  if (!n_out || (max > 0 && !host_out)) SDD_FAIL(SDD_EINVAL, "null argument");
+  const auto& m = tile_menu();
+  *n_out = (int32_t)m.size();
+  for (int32_t k = 0; k < max && k < (int32_t)m.size(); ++k) host_out[k] = m[k];
+  return SDD_OK;
+}

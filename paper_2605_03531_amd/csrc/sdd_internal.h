@@ -1,0 +1,181 @@
+// Internal declarations of libspotdd: the plan, the workspace layout and the
+// kernel launchers. Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "spotdd.h"
+
+namespace sdd {
+
+// Records the message returned by sdd_last_error() on this thread.
+void set_error(const char* fmt, ...);
+void clear_error();
+
+#define SDD_HIP_TRY(expr)                                                        \
+  do {                                                                           \
+    hipError_t e_ = (expr);                                                      \
+    if (e_ != hipSuccess) {                                                      \
+      ::sdd::set_error("%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                       __LINE__);                                                \
+      return SDD_EDEVICE;                                                        \
+    }                                                                            \
+  } while (0)
+
+#define SDD_FAIL(code, ...)          \
+  do {                               \
+    ::sdd::set_error(__VA_ARGS__);   \
+    return code;                     \
+  } while (0)
+
+constexpr double kDispersionConstant = 4.148808e3;  // s MHz^2 pc^-1 cm^3
+
+// Brackets one stage's launches with HIP events on its stream while timing is
+// enabled (sdd_profile_enable); does nothing otherwise.
+class StageTimer {
+ public:
+  StageTimer(int stage, hipStream_t s);
+  ~StageTimer();
+  StageTimer(const StageTimer&) = delete;
+  StageTimer& operator=(const StageTimer&) = delete;
+
+ private:
+  int stage_;
+  hipStream_t s_;
+  hipEvent_t a_{}, b_{};
+  bool active_ = false;
+};
+
+struct Range {
+  int32_t dec = 1;
+  std::vector<double> dms;
+  std::vector<int32_t> delays;  // host, [ndm][nchan]
+  int32_t max_delay = 0;
+  int32_t dm_offset = 0;
+  sdd_tile tile{};
+  int32_t ndm() const { return (int32_t)dms.size(); }
+};
+
+// Offsets (bytes) of every region of the per-call workspace.
+struct WsLayout {
+  int64_t ct_off = -1, ct_pitch = 0;            // corner-turned input [C][ct_pitch] u8
+  std::vector<int32_t> decs;                     // distinct decimations > 1, ascending
+  std::vector<int64_t> dec_off, dec_pitch, dec_len;  // u16 [C][pitch] each
+  int64_t plane_off[SDD_MAX_RANGES] = {0};       // library planes (with_planes only)
+  int64_t plane_pitch[SDD_MAX_RANGES] = {0};     // elements
+  int64_t cellres_off = 0;   // [sum_r ndm_r * ncells_r * nw] {u32 B, i32 j}
+  int64_t moments_off = 0;   // [ndm_total] {u64 s1, u64 s2}
+  int64_t cellbest_off = 0;  // [sum_r ndm_r * ncells_r] {f64 snr, i32 j, i32 w}
+  int64_t rowcnt_off = 0;    // [ndm_total] i32
+  int64_t rowoff_off = 0;    // [ndm_total + 1] i32
+  int64_t search_cells = 0;  // sum_r ndm_r * ncells_r
+  int64_t total = 0;         // bytes without library planes
+  int64_t total_planes = 0;  // bytes with library planes
+};
+
+// Per-call geometry derived from nsamp_in (see spotdd.h, "extent").
+struct CallGeom {
+  sdd_geometry g{};
+  WsLayout ws;
+  int64_t cell_base[SDD_MAX_RANGES] = {0};  // first global cell of range r
+};
+
+}  // namespace sdd
+
+struct sdd_plan {
+  int32_t nchan = 0, layout = 0, device = 0, cand_block = 1024;
+  float threshold = 0.f;
+  double t_samp = 0.0;
+  std::vector<double> freqs;
+  std::vector<int32_t> widths;
+  int32_t w_max = 1;
+  std::vector<sdd::Range> ranges;
+  int64_t overlap = 0;
+  int32_t ndm_total = 0;
+  int32_t dec_max = 1;
+
+  // device copies, made on first use
+  mutable std::mutex mu;
+  mutable int uploaded_device = -1;
+  mutable std::vector<int32_t*> d_delays;  // per range, [nchan][ndm_r]
+  mutable int32_t* d_widths = nullptr;
+
+  int32_t cells_for(int64_t n_owned_r) const {
+    return widths.empty() ? 0 : (int32_t)((n_owned_r + cand_block - 1) / cand_block);
+  }
+};
+
+namespace sdd {
+
+sdd_status plan_geometry(const sdd_plan* p, int64_t nsamp_in, CallGeom* out);
+sdd_status plan_upload(const sdd_plan* p);
+bool tile_in_menu(const sdd_tile& t);
+const std::vector<sdd_tile>& tile_menu();
+// Largest delay difference across any DM tile of dm_tile consecutive trials of
+// range r, over all channels (LDS window sizing).
+int32_t range_span(const sdd_plan* p, int32_t r, int32_t dm_tile);
+sdd_status check_tile_fits(const sdd_plan* p, int32_t r, const sdd_tile& t);
+sdd_tile default_tile(const sdd_plan* p, int32_t r);
+
+// ---- kernel launchers (k_*.hip) ----------------------------------------
+
+hipError_t launch_corner_turn(const uint8_t* in, int64_t nsamp, int64_t in_pitch, int32_t nchan,
+                              uint8_t* out, int64_t out_pitch, hipStream_t s);
+// out[c][j] = sum_{k<factor} in[c][j*factor+k], j < out_len; in is u8 or u16.
+hipError_t launch_decimate(const void* in, int in_bytes, int64_t in_pitch, int32_t nchan,
+                           int32_t factor, uint16_t* out, int64_t out_pitch, int64_t out_len,
+                           hipStream_t s);
+
+struct DedispArgs {
+  const void* x;          // channel rows of the range's input (u8 or u16)
+  int32_t elem_bytes;     // 1 or 2
+  int64_t x_pitch;        // elements between channel rows
+  int64_t x_len;          // valid samples per row
+  int32_t nchan;
+  const int32_t* delays;  // device [nchan][ndm]
+  int32_t ndm;
+  uint32_t* plane;
+  int64_t plane_pitch;    // elements
+  int64_t cols;           // columns to produce
+  int32_t max_val;        // largest input value (255 * dec)
+  sdd_tile tile;
+  int32_t span;           // largest delay difference over a DM tile of the chosen shape
+};
+hipError_t launch_dedisperse(const DedispArgs& a, hipStream_t s);
+
+struct SearchRange {
+  const uint32_t* plane;
+  int64_t pitch;
+  int64_t n_owned;     // N_r
+  int32_t ndm;
+  int32_t dm_offset;   // global trial index of row 0
+  int32_t ncells;
+  int32_t pad;
+  int64_t cell_base;   // global cell index of (row 0, cell 0)
+};
+struct SearchArgs {
+  SearchRange r[SDD_MAX_RANGES];
+  int32_t nranges;
+  int32_t ndm_total;
+  int32_t nwidths;
+  int32_t w_max;
+  int32_t widths[SDD_MAX_WIDTHS];
+  int32_t cand_block;
+  float threshold;
+  int32_t max_cells;     // max_r ncells_r
+  int32_t cap;
+  uint8_t* ws;           // workspace base
+  int64_t cellres_off, moments_off, cellbest_off, rowcnt_off, rowoff_off;
+  sdd_dm_best* best;
+  sdd_dm_stats* stats;   // may be null
+  sdd_candidate* cands;  // may be null when cap == 0
+  int32_t* ncand;
+};
+hipError_t launch_search(const SearchArgs& a, hipStream_t s);
+
+}  // namespace sdd

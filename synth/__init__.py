@@ -69,11 +69,16 @@ def filterbank(seed: int, nchan: int, nsamp: int, mean: float = 128.0,
 
 
 def inject_pulse(x: np.ndarray, offsets: np.ndarray, t0: int, width: int,
-                 amp: float) -> int:
-    """Add a top-hat pulse in place: x[c][t0 + offsets[c] + k] += rint(amp)
-    for k < width, saturating at 255. Samples outside the array are skipped.
-    Returns the number of saturated samples."""
-    inc = int(np.rint(amp))
+                 amp: float, seed: int = 0) -> int:
+    """Add a top-hat pulse in place: x[c][t0 + offsets[c] + k] gains amp
+    counts for k < width, saturating at 255. A whole amp is added exactly; a
+    fractional amp is dithered (floor(amp) plus one with probability
+    frac(amp), from a stream seeded by (seed, t0, width)), so the expected
+    increment is amp. Samples outside the array are skipped. Returns the
+    number of saturated samples."""
+    base = int(np.floor(amp))
+    frac = float(amp) - base
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, t0, width, 99])))
     nchan, nsamp = x.shape
     clipped = 0
     for c in range(nchan):
@@ -81,6 +86,9 @@ def inject_pulse(x: np.ndarray, offsets: np.ndarray, t0: int, width: int,
         lo, hi = max(a, 0), min(a + width, nsamp)
         if lo >= hi:
             continue
+        inc = np.full(hi - lo, base, dtype=np.int32)
+        if frac > 0.0:
+            inc += (rng.random(hi - lo) < frac).astype(np.int32)
         seg = x[c, lo:hi].astype(np.int32) + inc
         clipped += int(np.count_nonzero(seg > 255))
         x[c, lo:hi] = np.clip(seg, 0, 255).astype(np.uint8)

@@ -1,0 +1,165 @@
+"""Host-only checks of the C ABI (no GPU calls): the library loads and
+exports every declared symbol; plan tables, geometry and argument errors."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+import paper_2605_03531_amd as sdd
+from paper_2605_03531_amd import _capi as A
+
+
+def test_library_exports_every_header_symbol():
+    names = sdd.header_functions()
+    assert len(names) >= 15
+    L = sdd.lib()
+    missing = [n for n in names if not hasattr(L, n)]
+    assert missing == []
+    assert L.sdd_abi_version() == 1
+
+
+def test_struct_sizes_match_c_layout():
+    assert C.sizeof(A.PlanDesc) == 72
+    assert C.sizeof(A.Candidate) == 24
+    assert C.sizeof(A.DmBest) == 16
+    assert C.sizeof(A.DmStats) == 40
+    assert C.sizeof(A.DmRange) == 32
+
+
+def test_tiny_plan_delays_and_geometry():
+    w = synth.tiny(oracle.delay_table, with_data=False)
+    p = sdd.Plan(w.freqs_mhz, w.t_samp, dm_list=w.dm_list, widths=w.widths)
+    np.testing.assert_array_equal(p.delays(0), oracle.delay_table(w.freqs_mhz, w.dm_list, w.t_samp))
+    np.testing.assert_array_equal(p.dms(0), w.dm_list)
+    spec = oracle.make_plan(w.freqs_mhz, w.t_samp, dm_list=w.dm_list, widths=w.widths)
+    assert p.overlap == spec.overlap == 4517
+    g = p.geometry(w.nsamp)
+    assert g["n_owned"] == 3675 and g["plane_cols"] == [3690] and g["ncells"] == [4]
+
+
+def test_full_band_delays_bit_exact():
+    """All 2048 x 4096 delays of the full-band workload equal the oracle's."""
+    f = np.linspace(750.0, 550.0, 4096)
+    dms = np.linspace(0.0, 1000.0, 2048)
+    p = sdd.Plan(f, 81.92e-6, dm_list=dms)
+    d = p.delays(0)
+    o = oracle.delay_table(f, dms, 81.92e-6)
+    assert (d == o).all()
+    assert p.max_delay == [77385] and p.overlap == 77385
+
+
+def test_multi_range_tables_bit_exact():
+    f = np.linspace(750.0, 550.0, 512)
+    p = sdd.Plan(f, 81.92e-6, ranges=synth.MULTI_RANGES, widths=[1 << k for k in range(9)])
+    spec = oracle.make_plan(f, 81.92e-6, ranges=synth.MULTI_RANGES,
+                            widths=[1 << k for k in range(9)])
+    assert p.ndm == [1000, 1000, 800, 800, 750]
+    assert p.decimation == [1, 2, 4, 8, 16]
+    assert p.dm_offset == [0, 1000, 2000, 2800, 3600]
+    for r, rs in enumerate(spec.ranges):
+        np.testing.assert_array_equal(p.dms(r), rs.dms)
+        np.testing.assert_array_equal(p.delays(r), rs.delays)
+        assert p.max_delay[r] == rs.max_delay
+    assert p.overlap == spec.overlap
+    T = spec.overlap + (1 << 19)
+    g = p.geometry(T)
+    assert g["n_owned_r"] == spec.owned(T) == [1 << 19 >> k for k in range(5)]
+
+
+def test_unsorted_frequencies_reference_the_max():
+    f = np.array([400.0, 500.0, 300.0, 450.0])
+    p = sdd.Plan(f, 1e-3, dm_list=[0.0, 50.0, 100.0])
+    np.testing.assert_array_equal(p.delays(0), oracle.delay_table(f, [0.0, 50.0, 100.0], 1e-3))
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(widths=[2, 1]), A.SDD_EINVAL),
+    (dict(widths=[0, 1]), A.SDD_EINVAL),
+    (dict(widths=[8193]), A.SDD_EINVAL),
+    (dict(t_samp=0.0), A.SDD_EINVAL),
+    (dict(dm_list=[-1.0]), A.SDD_EINVAL),
+    (dict(freqs=[500.0, -3.0]), A.SDD_EINVAL),
+    (dict(both=True), A.SDD_EINVAL),
+    (dict(neither=True), A.SDD_EINVAL),
+    (dict(ranges=[(0.0, 10.0, 1.0, 0)]), A.SDD_EINVAL),
+    (dict(ranges=[(0.0, 10.0, 0.0, 1)]), A.SDD_EINVAL),
+    (dict(cand_block=-5), A.SDD_EINVAL),
+    # 65536 channels * 255 * 512 >= 2^32: boxcar sums could overflow
+    (dict(freqs=list(np.linspace(500, 300, 65536)), widths=[512]), A.SDD_ERANGE),
+])
+def test_plan_argument_errors(kw, status):
+    freqs = kw.get("freqs", [500.0, 400.0, 300.0])
+    t = kw.get("t_samp", 1e-3)
+    dm_list = kw.get("dm_list", [0.0, 10.0])
+    ranges = kw.get("ranges")
+    if ranges is not None:
+        dm_list = None
+    if kw.get("both"):
+        ranges = [(0.0, 10.0, 1.0, 1)]
+    if kw.get("neither"):
+        dm_list = None
+    with pytest.raises(sdd.SddError) as ei:
+        sdd.Plan(freqs, t, dm_list=dm_list, ranges=ranges, widths=kw.get("widths", ()),
+                 cand_block=kw.get("cand_block", 1024))
+    assert ei.value.status == status
+    assert len(A.lib().sdd_last_error()) > 0
+
+
+def test_geometry_rejects_short_input():
+    p = sdd.Plan([500.0, 300.0], 1e-3, ranges=[(0.0, 10.0, 1.0, 1), (10.0, 20.0, 1.0, 4)],
+                 widths=[1, 2])
+    O = p.overlap
+    with pytest.raises(sdd.SddError) as ei:
+        p.geometry(O + 3)
+    assert ei.value.status == A.SDD_EINVAL
+    g = p.geometry(O + 4)
+    assert g["n_owned_r"] == [4, 1]
+
+
+def test_compute_calls_validate_before_touching_the_device():
+    p = sdd.Plan([500.0, 300.0], 1e-3, dm_list=[0.0, 5.0], widths=[1])
+    T = p.overlap + 100
+    L = A.lib()
+    planes = (C.c_void_p * 1)(1)
+    pitch = (C.c_int64 * 1)(4)
+    # null input
+    assert L.sdd_dedisperse(p.handle, None, T, T, planes, pitch, 1, 1 << 20, None) == A.SDD_EINVAL
+    # pitch smaller than the plane's columns
+    assert L.sdd_dedisperse(p.handle, 1, T, T, planes, pitch, 1, 1 << 20, None) == A.SDD_EINVAL
+    # input pitch smaller than the row
+    g = p.geometry(T)
+    pitch2 = (C.c_int64 * 1)(g["plane_cols"][0])
+    assert L.sdd_dedisperse(p.handle, 1, T, T - 1, planes, pitch2, 1, 1 << 20, None) == A.SDD_EINVAL
+    # too short an input
+    assert L.sdd_dedisperse(p.handle, 1, p.overlap, T, planes, pitch2, 1, 1 << 20, None) == A.SDD_EINVAL
+    # workspace too small
+    assert L.sdd_dedisperse(p.handle, 1, T, T, planes, pitch2, 1, 0, None) == A.SDD_ENOMEM
+    # search on a plane-only plan
+    q = sdd.Plan([500.0, 300.0], 1e-3, dm_list=[0.0])
+    assert L.sdd_search_boxcar(q.handle, planes, pitch2, T, 1, 1, 1, 1, 1, 1, 1 << 20,
+                               None) == A.SDD_EINVAL
+    # null candidate buffer with a positive capacity
+    assert L.sdd_search_boxcar(p.handle, planes, pitch2, T, 1, 1, None, 4, 1, 1, 1 << 20,
+                               None) == A.SDD_EINVAL
+
+
+def test_tile_menu_and_set_tile():
+    menu = sdd.tile_menu()
+    assert (0, 0, 0, 0, 0, 0) in menu
+    p = sdd.Plan([500.0, 300.0], 1e-3, dm_list=[0.0, 5.0])
+    for t in menu:
+        p.set_tile(t)
+        assert p.get_tile(0) == t
+    with pytest.raises(sdd.SddError):
+        p.set_tile((9, 9, 9, 9, 9, 9))
+
+
+def test_single_hip_runtime_in_process():
+    """The library must share torch's HIP runtime: two copies of libamdhip64
+    in one process make device selection fail."""
+    sdd.lib()
+    import torch  # noqa: F401
+    maps = {l.split()[-1] for l in open("/proc/self/maps") if "libamdhip64" in l}
+    assert len(maps) == 1, maps
