@@ -237,6 +237,130 @@ sdd_status sdd_dedisperse_search(const sdd_plan* plan, const uint8_t* d_in, int6
                                  int32_t* d_ncand, void* d_workspace, int64_t ws_bytes,
                                  void* stream);
 
+/* ---- batches of chunks (many beams, uneven lengths) ---------------------- */
+
+/* One chunk of one beam in a batch; fields as in sdd_dedisperse_search.
+ * d_planes may be NULL (planes live in the batch workspace, not returned);
+ * plans without widths only dedisperse (d_best ... d_ncand unused). */
+typedef struct sdd_batch_item {
+  const sdd_plan* plan;
+  const uint8_t* d_in;
+  int64_t nsamp_in;
+  int64_t in_pitch;
+  uint32_t* const* d_planes;
+  const int64_t* plane_pitch;
+  sdd_dm_best* d_best;
+  sdd_dm_stats* d_stats;
+  sdd_candidate* d_cands;
+  int32_t cap;
+  int32_t reserved;
+  int32_t* d_ncand;
+} sdd_batch_item;
+
+/* flags of sdd_batch_dedisperse_search */
+enum {
+  SDD_BATCH_PER_ITEM = 1, /* one launch per (chunk, range) instead of the persistent
+                             multi-chunk dedispersion launch */
+  SDD_BATCH_GRAPH = 2     /* capture the batch's launch sequence as a HIP graph on the
+                             first call and replay it on later calls with identical
+                             items, flags, workspace and stream (EINVAL on the null
+                             stream, which cannot be captured) */
+};
+
+/* Workspace bytes for a batch (all items on one device). */
+sdd_status sdd_batch_workspace_size(const sdd_batch_item* items, int32_t n, int64_t* bytes);
+/* Dedisperses and searches every item (Section 2.1 over many beams, the
+ * beam-level parallelism of Section 2.2). By default the dedispersion of all
+ * items whose DM ranges share an LDS tile shape runs as one persistent launch
+ * whose workgroups pull tiles from per-XCD queues, so beams of uneven length
+ * leave no tail per beam. Results equal per-item sdd_dedisperse_search calls
+ * bit for bit. A graph replay (SDD_BATCH_GRAPH) re-runs the captured launches
+ * on the same buffers: the caller rewrites inputs in place between calls. */
+sdd_status sdd_batch_dedisperse_search(const sdd_batch_item* items, int32_t n, int32_t flags,
+                                       void* d_ws, int64_t ws_bytes, void* stream);
+/* Destroys every cached batch graph. */
+sdd_status sdd_batch_graph_clear(void);
+
+/* ---- streaming server (continuous batching of many beams) ---------------- */
+
+typedef struct sdd_server sdd_server;
+typedef struct sdd_stream sdd_stream;
+
+/* flags of sdd_server_desc */
+enum { SDD_SERVER_FAKE = 1 /* no GPU: batches sleep fake_exec_us and yield empty
+                              results (for testing the scheduling logic) */ };
+
+typedef struct sdd_server_desc {
+  int64_t hbm_budget;     /* device bytes the server may hold: rings + slot buffers */
+  int32_t device;
+  int32_t max_beams;      /* open streams at most */
+  int32_t nstreams;       /* batch slots (HIP streams) running concurrently, 1..16 */
+  int32_t max_batch;      /* output chunks per batch, 1..256 */
+  int32_t ring_chunks;    /* ring depth beyond the overlap, in chunks (>= 2) */
+  int32_t cap;            /* candidates kept per output chunk */
+  int32_t batch_flags;    /* SDD_BATCH_PER_ITEM or 0 (persistent launch) */
+  int32_t flags;          /* SDD_SERVER_FAKE */
+  int32_t fake_exec_us;   /* batch duration in fake mode */
+  int32_t reserved;
+} sdd_server_desc;
+
+/* One output chunk of one stream. best/cands are host memory owned by the
+ * server until sdd_result_release. Times are steady-clock nanoseconds:
+ * t_ready = the submit that completed the chunk's input returned, t_start =
+ * its batch was launched, t_done = its results reached host memory. */
+typedef struct sdd_result {
+  uint64_t tag;                /* the stream's tag */
+  int64_t chunk;               /* k: owned native samples [k*N, (k+1)*N) of the stream */
+  int32_t status;              /* SDD_OK or the device error of its batch */
+  int32_t ncand;               /* candidates found (may exceed the server's cap) */
+  int32_t ndm;                 /* entries of best */
+  int32_t reserved;
+  const sdd_dm_best* best;     /* [ndm] */
+  const sdd_candidate* cands;  /* [min(ncand, cap)] in (range, dm, sample) order */
+  int64_t t_ready_ns, t_start_ns, t_done_ns;
+  void* handle;
+} sdd_result;
+
+typedef struct sdd_server_stats {
+  int32_t open_streams;
+  int32_t queued_results;
+  int64_t hbm_used;
+  int64_t batches;
+  int64_t chunks;
+  double busy_ms;              /* summed batch time (launch to results on host) */
+} sdd_server_stats;
+
+/* Starts the scheduler and completion threads. */
+sdd_status sdd_server_create(const sdd_server_desc* desc, sdd_server** out);
+/* Closes every open stream (waiting for their batches) and frees the server;
+ * unreleased results are freed too. */
+sdd_status sdd_server_destroy(sdd_server* server);
+/* Ring bytes a stream of this plan and chunk length would hold. */
+sdd_status sdd_stream_footprint(const sdd_server* server, const sdd_plan* plan,
+                                int64_t chunk_nsamp, int64_t* bytes);
+/* Opens a beam: time-major plan, chunks of chunk_nsamp samples (a multiple of
+ * the plan's largest decimation). SDD_EAGAIN if max_beams are open or the
+ * beam's ring (plus slot growth) does not fit the HBM budget. The plan must
+ * outlive the stream. */
+sdd_status sdd_stream_open(sdd_server* server, const sdd_plan* plan, int64_t chunk_nsamp,
+                           uint64_t tag, sdd_stream** out);
+/* Copies chunk seq (spectra [nsamp][nchan], host or device memory) into the
+ * beam's ring; the caller may reuse its buffer on return. seq must count
+ * 0, 1, 2, ... (SDD_ESTATE on a gap or after close). SDD_EAGAIN when the ring
+ * slot still holds samples of an unfinished output chunk: poll, then retry. */
+sdd_status sdd_stream_submit(sdd_stream* stream, const uint8_t* chunk, int64_t nsamp,
+                             uint64_t seq, int32_t on_device);
+/* Stops the beam: no more submits, unscheduled output chunks are dropped,
+ * scheduled ones finish (their results stay queued); frees the ring. */
+sdd_status sdd_stream_close(sdd_stream* stream);
+/* Takes up to max finished results, waiting up to timeout_us (< 0: until one
+ * arrives or the server stops). SDD_ETIMEDOUT with *n_out = 0 if none came. */
+sdd_status sdd_stream_poll(sdd_server* server, sdd_result* out, int32_t max, int32_t timeout_us,
+                           int32_t* n_out);
+/* Returns a polled result's host memory to the server. */
+sdd_status sdd_result_release(sdd_server* server, sdd_result* result);
+sdd_status sdd_server_query(sdd_server* server, sdd_server_stats* out);
+
 /* ---- kernel timing (benchmarks) ----------------------------------------- */
 
 /* Stages whose kernels can be timed. */

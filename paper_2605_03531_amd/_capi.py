@@ -4,7 +4,7 @@ Loading fails loudly when libspotdd.so is missing: there is no fallback path.
 """
 from __future__ import annotations
 
-import ctypes as C
+import ctypes as C  # noqa: F401
 import os
 import re
 
@@ -70,6 +70,33 @@ class Tile(C.Structure):
                 ("pairs_per_lane", i32), ("chan_stage", i32)]
 
 
+class BatchItem(C.Structure):
+    _fields_ = [("plan", vp), ("d_in", vp), ("nsamp_in", i64), ("in_pitch", i64),
+                ("d_planes", C.POINTER(vp)), ("plane_pitch", C.POINTER(i64)), ("d_best", vp),
+                ("d_stats", vp), ("d_cands", vp), ("cap", i32), ("reserved", i32),
+                ("d_ncand", vp)]
+
+
+SDD_BATCH_PER_ITEM, SDD_BATCH_GRAPH = 1, 2
+SDD_SERVER_FAKE = 1
+
+
+class ServerDesc(C.Structure):
+    _fields_ = [("hbm_budget", i64), ("device", i32), ("max_beams", i32), ("nstreams", i32),
+                ("max_batch", i32), ("ring_chunks", i32), ("cap", i32), ("batch_flags", i32),
+                ("flags", i32), ("fake_exec_us", i32), ("reserved", i32)]
+
+
+class Result(C.Structure):
+    _fields_ = [("tag", u64), ("chunk", i64), ("status", i32), ("ncand", i32), ("ndm", i32),
+                ("reserved", i32), ("best", C.POINTER(DmBest)), ("cands", C.POINTER(Candidate)),
+                ("t_ready_ns", i64), ("t_start_ns", i64), ("t_done_ns", i64), ("handle", vp)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("open_streams", i32), ("queued_results", i32), ("hbm_used", i64),
+                ("batches", i64), ("chunks", i64), ("busy_ms", f64)]
+
 PlanP = vp
 
 _PROTOS = {
@@ -90,6 +117,18 @@ _PROTOS = {
                                 vp, i64, vp]),
     "sdd_dedisperse_search": (i32, [vp, vp, i64, i64, C.POINTER(vp), C.POINTER(i64), vp, vp,
                                     vp, i32, vp, vp, i64, vp]),
+    "sdd_batch_workspace_size": (i32, [C.POINTER(BatchItem), i32, C.POINTER(i64)]),
+    "sdd_batch_dedisperse_search": (i32, [C.POINTER(BatchItem), i32, i32, vp, i64, vp]),
+    "sdd_batch_graph_clear": (i32, []),
+    "sdd_server_create": (i32, [C.POINTER(ServerDesc), C.POINTER(vp)]),
+    "sdd_server_destroy": (i32, [vp]),
+    "sdd_stream_footprint": (i32, [vp, vp, i64, C.POINTER(i64)]),
+    "sdd_stream_open": (i32, [vp, vp, i64, u64, C.POINTER(vp)]),
+    "sdd_stream_submit": (i32, [vp, vp, i64, u64, i32]),
+    "sdd_stream_close": (i32, [vp]),
+    "sdd_stream_poll": (i32, [vp, C.POINTER(Result), i32, i32, C.POINTER(i32)]),
+    "sdd_result_release": (i32, [vp, C.POINTER(Result)]),
+    "sdd_server_query": (i32, [vp, C.POINTER(ServerStats)]),
     "sdd_profile_enable": (i32, [i32]),
     "sdd_profile_read": (i32, [i32, C.POINTER(f64), C.POINTER(i64)]),
 }

@@ -9,19 +9,6 @@
 namespace sdd {
 const char* last_error();
 
-namespace {
-
-struct DeviceGuard {
-  int prev = -1;
-  bool ok = false;
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev) == hipSuccess && hipSetDevice(dev) == hipSuccess) ok = true;
-  }
-  ~DeviceGuard() {
-    if (prev >= 0) (void)hipSetDevice(prev);
-  }
-};
-
 sdd_status check_planes(const sdd_plan* p, const CallGeom& cg, const void* const* planes,
                         const int64_t* pitch) {
   if (!planes || !pitch) SDD_FAIL(SDD_EINVAL, "null plane array or pitch array");
@@ -45,16 +32,18 @@ sdd_status check_input(const sdd_plan* p, const uint8_t* d_in, int64_t nsamp_in,
   return SDD_OK;
 }
 
-sdd_status run_dedisperse(const sdd_plan* p, const CallGeom& cg, const uint8_t* d_in,
-                          int64_t nsamp_in, int64_t in_pitch, uint32_t* const* planes,
-                          const int64_t* pitch, uint8_t* ws, hipStream_t s) {
+sdd_status prep_item(const sdd_plan* p, const CallGeom& cg, const uint8_t* d_in, int64_t nsamp_in,
+                     int64_t in_pitch, uint32_t* const* planes, const int64_t* pitch, uint8_t* ws,
+                     hipStream_t s, std::vector<DedispArgs>* jobs, int64_t ring_rows,
+                     int64_t ring_start) {
   const WsLayout& L = cg.ws;
   const uint8_t* src = d_in;
   int64_t src_pitch = in_pitch;
   if (p->layout == SDD_TIME_MAJOR) {
     uint8_t* ct = ws + L.ct_off;
     StageTimer tm(SDD_STAGE_CORNER_TURN, s);
-    SDD_HIP_TRY(launch_corner_turn(d_in, nsamp_in, in_pitch, p->nchan, ct, L.ct_pitch, s));
+    SDD_HIP_TRY(launch_corner_turn(d_in, nsamp_in, in_pitch, p->nchan, ct, L.ct_pitch, s,
+                                   ring_rows, ring_start));
     src = ct;
     src_pitch = L.ct_pitch;
   }
@@ -101,9 +90,21 @@ sdd_status run_dedisperse(const sdd_plan* p, const CallGeom& cg, const uint8_t* 
     a.cols = cg.g.plane_cols[r];
     a.max_val = 255 * R.dec;
     a.tile = R.tile;
-    a.span = 0;
+    a.span = R.tile_span;
     if (a.cols + R.max_delay > a.x_len)
       SDD_FAIL(SDD_EINVAL, "internal: range %zu input too short", r);
+    jobs->push_back(a);
+  }
+  return SDD_OK;
+}
+
+sdd_status run_dedisperse(const sdd_plan* p, const CallGeom& cg, const uint8_t* d_in,
+                          int64_t nsamp_in, int64_t in_pitch, uint32_t* const* planes,
+                          const int64_t* pitch, uint8_t* ws, hipStream_t s) {
+  std::vector<DedispArgs> jobs;
+  sdd_status st = prep_item(p, cg, d_in, nsamp_in, in_pitch, planes, pitch, ws, s, &jobs);
+  if (st != SDD_OK) return st;
+  for (const auto& a : jobs) {
     StageTimer tm(SDD_STAGE_DEDISPERSE, s);
     SDD_HIP_TRY(launch_dedisperse(a, s));
   }
@@ -150,7 +151,6 @@ sdd_status run_search(const sdd_plan* p, const CallGeom& cg, const uint32_t* con
   return SDD_OK;
 }
 
-}  // namespace
 }  // namespace sdd
 
 using namespace sdd;

@@ -1,9 +1,11 @@
 // Brute-force incoherent dedispersion kernels (Section 3.2: every trial DM
 // sums all channels along its delay curve; Section 2.1: many trial DMs).
 //   plane[i][j] = sum_c x[c][j + delay[c][i]],  j < cols   (exact uint32)
+#include "k_dedisp_lds.h"
 #include "sdd_internal.h"
 
 namespace sdd {
+int lds_shape_index(const sdd_tile& t);
 namespace {
 
 // Direct kernel: one thread per (trial, 4 consecutive columns), a plain
@@ -46,8 +48,35 @@ __global__ __launch_bounds__(256) void k_dedisp_direct(const Tin* __restrict__ x
 
 }  // namespace
 
+int lds_args_for(const DedispArgs& a, LdsArgs* out) {
+  const int shape = lds_shape_index(a.tile);
+  const bool plane_ok = ((uintptr_t)a.plane % 16 == 0) && (a.plane_pitch % 4 == 0);
+  if (shape < 0 || a.elem_bytes != 1 || !plane_ok || a.cols <= 0 || a.ndm <= 0) return -1;
+  const LdsShape& sh = kLdsShapes[shape];
+  LdsArgs& l = *out;
+  l = LdsArgs{};
+  l.x = (const uint8_t*)a.x;
+  l.x_pitch = a.x_pitch;
+  l.x_len = a.x_len;
+  l.nchan = a.nchan;
+  l.ndm = a.ndm;
+  l.delays = a.delays;
+  l.plane = a.plane;
+  l.plane_pitch = a.plane_pitch;
+  l.cols = a.cols;
+  const int32_t tt = 512 * sh.m * sh.wt, dt = sh.d * sh.wd;
+  l.win = lds_window(tt, a.span);
+  l.n_dtiles = (a.ndm + dt - 1) / dt;
+  l.n_ttiles = (int32_t)((a.cols + tt - 1) / tt);
+  l.aligned = ((uintptr_t)a.x % 16 == 0) && (a.x_pitch % 16 == 0);
+  return shape;
+}
+
 hipError_t launch_dedisperse(const DedispArgs& a, hipStream_t s) {
   if (a.cols <= 0 || a.ndm <= 0) return hipSuccess;
+  LdsArgs lds_args;
+  const int shape = lds_args_for(a, &lds_args);
+  if (shape >= 0) return launch_dedisperse_lds(lds_args, shape, s);
   const int64_t per_block = 256 * 4;
   const int64_t nyb = (a.cols + per_block - 1) / per_block;
   if (nyb > 65535) return hipErrorInvalidValue;

@@ -1,0 +1,53 @@
+// Arguments and shape menu of the LDS-tiled dedispersion kernel.
+#pragma once
+
+#include "sdd_internal.h"
+
+namespace sdd {
+
+struct LdsArgs {
+  const uint8_t* x;       // channel rows, uint8
+  int64_t x_pitch;        // bytes between rows
+  int64_t x_len;          // valid samples per row
+  int32_t nchan;
+  int32_t ndm;
+  const int32_t* delays;  // device [nchan][ndm]
+  uint32_t* plane;
+  int64_t plane_pitch;
+  int64_t cols;
+  int32_t win;            // LDS window bytes per copy (multiple of 16)
+  int32_t n_dtiles, n_ttiles;
+  int32_t aligned;        // x and x_pitch are 16-byte aligned
+};
+
+// Compile-time shape of one instantiation.
+struct LdsShape {
+  int d;      // trials per wavefront
+  int m;      // 512-sample chunks per lane group
+  int wd;     // wavefronts along DM
+  int wt;     // wavefronts along time
+  int cs;     // channels per LDS stage
+  int nld;    // 16-byte staging loads per thread per stage
+};
+
+extern const LdsShape kLdsShapes[];
+extern const int kNumLdsShapes;
+
+// Jobs of one persistent launch (kernel argument, so at most kMaxJobs).
+constexpr int kMaxJobs = 32;
+struct MultiArgs {
+  LdsArgs jobs[kMaxJobs];
+  int32_t tile_base[kMaxJobs + 1];  // first global tile of each job; [njobs] = total
+  int32_t njobs;
+  uint32_t* counters;               // 8 device counters, one per XCD
+};
+
+hipError_t launch_dedisperse_lds(const LdsArgs& a, int shape, hipStream_t s);
+// LDS-kernel arguments of one job; returns its shape index, or -1 when the
+// job must take the direct kernel (decimated input, unaligned plane, ...).
+int lds_args_for(const DedispArgs& a, LdsArgs* out);
+// All jobs must fit the shape; max_win = largest job window.
+hipError_t launch_dedisperse_lds_multi(const MultiArgs& m, int32_t max_win, int shape,
+                                       hipStream_t s);
+
+}  // namespace sdd

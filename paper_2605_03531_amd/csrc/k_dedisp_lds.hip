@@ -1,0 +1,353 @@
+// LDS-tiled brute-force dedispersion of uint8 channel rows (Section 3.2:
+// every trial DM sums all channels along its delay curve):
+//   plane[i][j] = sum_c x[c][j + delay[c][i]]
+//
+// One workgroup owns a tile of DT = D*WD trials x TT = 512*M*WT samples and
+// walks the channels in stages of CS. For each channel it stages the window
+// of input bytes every trial of the tile needs, [t0 + d(c,i0), t0 + TT +
+// d(c,i_last)), in LDS twice: as loaded (copy 0) and shifted by 4 bytes
+// (copy 1). A lane owns 8 consecutive samples per chunk; for trial i it reads
+// 12 bytes (one 64-bit and one 32-bit LDS read, both aligned) from the copy
+// that leaves the wanted 8 bytes at an offset s < 4, and v_perm both aligns
+// and widens them into four pairs of 16-bit fields. v_add3 adds two channels
+// into each packed accumulator; every 256 channels the packed fields are
+// flushed into uint32 sums (256 * 255 < 2^16 keeps the fields exact).
+//
+// Wavefronts split the tile: WD groups along DM (D trials each) x WT groups
+// along time (M chunks of 512 samples each). Lanes of a chunk read
+// consecutive 8-byte words, so LDS reads are free of bank conflicts.
+// Workgroups are ordered DM-tile-major and each XCD takes a contiguous run of
+// tiles, so the concurrently running tiles of one XCD are neighbours in time
+// whose input windows overlap in that XCD's L2.
+#include "k_dedisp_lds.h"
+
+namespace sdd {
+namespace {
+
+__device__ __forceinline__ uint32_t sel_pair(uint32_t s) {
+  // bytes s, s+1 of an 8-byte (hi:lo) pair into the low bytes of two 16-bit
+  // fields; selector byte 0x0c yields zero
+  return s | 0x00000c00u | ((s + 1u) << 16) | 0x0c000000u;
+}
+
+// One DT x TT tile of one job. Every thread of the workgroup calls it; it
+// returns after a barrier, so the caller may reuse the LDS at once.
+template <int D, int M, int WD, int WT, int CS, int NLD>
+__device__ __forceinline__ void dd_tile(const LdsArgs a, int32_t dtile, int32_t ttile,
+                                        uint8_t* __restrict__ lds) {
+  constexpr int NT = 64 * WD * WT;
+  constexpr int DT = D * WD;
+  constexpr int TW = 512 * M;   // samples per time group of waves
+  constexpr int TT = TW * WT;
+  const int32_t i0 = dtile * DT;
+  const int64_t t0 = (int64_t)ttile * TT;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wd = wave % WD, wt = wave / WD;
+  const int32_t ndm = a.ndm, nchan = a.nchan;
+  const int32_t* __restrict__ dcm = a.delays;
+
+  int32_t iw[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    const int32_t i = i0 + wd * D + d;
+    iw[d] = i < ndm ? i : ndm - 1;
+  }
+
+  const int32_t win = a.win;            // bytes per copy, multiple of 16
+  const int32_t slot = 2 * win;         // copy 0 + copy 1
+  const int32_t buf = CS * slot;
+  const int32_t wq = win >> 4;          // 16-byte elements per window
+
+  uint32_t acc[D][M][4];
+  uint32_t wide[D][M][8];
+#pragma unroll
+  for (int d = 0; d < D; ++d)
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) acc[d][m][k] = 0u;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) wide[d][m][k] = 0u;
+    }
+
+  // ---- staging: global -> registers -> two LDS copies ----
+  uint4 st[NLD];
+  auto load_stage = [&](int32_t cbase) {
+#pragma unroll
+    for (int k = 0; k < NLD; ++k) {
+      const int32_t e = tid + k * NT;
+      const int32_t cs = e / wq;
+      const int32_t q = e - cs * wq;
+      const int32_t c = cbase + cs;
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (cs < CS && c < nchan) {
+        const int64_t g = t0 + (int64_t)(dcm[(int64_t)c * ndm + i0] & ~15) + 16 * q;
+        const uint8_t* src = a.x + (int64_t)c * a.x_pitch + g;
+        if (a.aligned && g + 16 <= a.x_len) {
+          v = *reinterpret_cast<const uint4*>(src);
+        } else {
+          uint32_t w[4] = {0u, 0u, 0u, 0u};
+          for (int bb = 0; bb < 16; ++bb)
+            if (g + bb < a.x_len) w[bb >> 2] |= (uint32_t)src[bb] << (8 * (bb & 3));
+          v = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+      }
+      st[k] = v;
+    }
+  };
+  auto store_stage = [&](int32_t which) {
+    uint8_t* base = lds + which * buf;
+#pragma unroll
+    for (int k = 0; k < NLD; ++k) {
+      const int32_t e = tid + k * NT;
+      const int32_t cs = e / wq;
+      const int32_t q = e - cs * wq;
+      if (cs < CS) {
+        uint8_t* c0 = base + cs * slot + 16 * q;  // copy 0
+        uint8_t* c1 = c0 + win;                   // copy 1: byte j holds window byte j + 4
+        *reinterpret_cast<uint4*>(c0) = st[k];
+        if (q > 0) *reinterpret_cast<uint32_t*>(c1 - 4) = st[k].x;
+        *reinterpret_cast<uint2*>(c1) = make_uint2(st[k].y, st[k].z);
+        *reinterpret_cast<uint32_t*>(c1 + 8) = st[k].w;
+      }
+    }
+  };
+
+  auto flush = [&]() {
+#pragma unroll
+    for (int d = 0; d < D; ++d)
+#pragma unroll
+      for (int m = 0; m < M; ++m)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          wide[d][m][2 * k] += acc[d][m][k] & 0xffffu;
+          wide[d][m][2 * k + 1] += acc[d][m][k] >> 16;
+          acc[d][m][k] = 0u;
+        }
+  };
+
+  // Delays of the next stage travel with its data: lane k < CS*(D+1) loads
+  // one entry (slot k/(D+1); entry 0 = the tile's first trial, entry 1+d =
+  // this wavefront's trial d) through the vector memory path, so the compute
+  // loop holds no scalar-memory waits that would also drain its LDS reads.
+  // A channel past nchan gets delay 0 and an all-zero window.
+  constexpr int DE = D + 1;
+  constexpr int NDV = (CS * DE + 63) / 64;  // VGPRs holding one stage's delays
+  auto load_delays = [&](int32_t cbase, int32_t (&out)[NDV]) {
+#pragma unroll
+    for (int v = 0; v < NDV; ++v) {
+      const int32_t k = 64 * v + lane;
+      const int32_t cs = k / DE, e = k - cs * DE;
+      const int32_t c = cbase + cs;
+      int32_t i = e == 0 ? i0 : i0 + wd * D + e - 1;
+      i = i < ndm ? i : ndm - 1;
+      out[v] = (k < CS * DE && c < nchan) ? dcm[(int64_t)c * ndm + i] : 0;
+    }
+  };
+  // entry k of the current stage, as a wave-uniform scalar
+#define SDD_DELAY(k) __builtin_amdgcn_readlane(dcur[(k) / 64], (k) % 64)
+
+  const int32_t nstages = (nchan + CS - 1) / CS;
+  const int32_t lane_off = 8 * lane + TW * wt;
+  load_stage(0);
+  int32_t dnext[NDV];
+  load_delays(0, dnext);
+  store_stage(0);
+  __syncthreads();
+  for (int32_t s = 0; s < nstages; ++s) {
+    const int32_t cbase = s * CS;
+    int32_t dcur[NDV];
+#pragma unroll
+    for (int v = 0; v < NDV; ++v) dcur[v] = dnext[v];
+    if (s + 1 < nstages) {
+      load_stage(cbase + CS);
+      load_delays(cbase + CS, dnext);
+    }
+    const uint8_t* bufp = lds + (s & 1) * buf + lane_off;
+#pragma unroll
+    for (int cc = 0; cc < CS; cc += 2) {
+      const int32_t baseA = SDD_DELAY(cc * DE) & ~15;
+      const int32_t baseB = SDD_DELAY((cc + 1) * DE) & ~15;
+      const uint8_t* slotA = bufp + cc * slot;
+      const uint8_t* slotB = slotA + slot;
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const int32_t oA = SDD_DELAY(cc * DE + 1 + d) - baseA;
+        const int32_t oB = SDD_DELAY((cc + 1) * DE + 1 + d) - baseB;
+        // copy 1 when the byte offset within the 8-byte word is >= 4
+        const int32_t adA = (oA & ~7) + ((oA & 4) ? win : 0);
+        const int32_t adB = (oB & ~7) + ((oB & 4) ? win : 0);
+        const uint32_t sA0 = sel_pair(oA & 3), sA2 = sel_pair((oA & 3) + 2);
+        const uint32_t sB0 = sel_pair(oB & 3), sB2 = sel_pair((oB & 3) + 2);
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+          const uint8_t* pA = slotA + adA + 512 * m;
+          const uint8_t* pB = slotB + adB + 512 * m;
+          const uint2 a01 = *reinterpret_cast<const uint2*>(pA);
+          const uint32_t a2 = *reinterpret_cast<const uint32_t*>(pA + 8);
+          const uint2 b01 = *reinterpret_cast<const uint2*>(pB);
+          const uint32_t b2 = *reinterpret_cast<const uint32_t*>(pB + 8);
+          acc[d][m][0] += __builtin_amdgcn_perm(a01.y, a01.x, sA0) +
+                          __builtin_amdgcn_perm(b01.y, b01.x, sB0);
+          acc[d][m][1] += __builtin_amdgcn_perm(a01.y, a01.x, sA2) +
+                          __builtin_amdgcn_perm(b01.y, b01.x, sB2);
+          acc[d][m][2] += __builtin_amdgcn_perm(a2, a01.y, sA0) +
+                          __builtin_amdgcn_perm(b2, b01.y, sB0);
+          acc[d][m][3] += __builtin_amdgcn_perm(a2, a01.y, sA2) +
+                          __builtin_amdgcn_perm(b2, b01.y, sB2);
+        }
+      }
+    }
+    if (((cbase + CS) & 255) == 0 || s + 1 == nstages) flush();
+    if (s + 1 < nstages) store_stage((s + 1) & 1);
+    __syncthreads();
+  }
+
+#undef SDD_DELAY
+
+  // ---- store the tile ----
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    const int32_t i = i0 + wd * D + d;
+    if (i >= ndm) break;
+    uint32_t* row = a.plane + (int64_t)i * a.plane_pitch;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const int64_t j = t0 + lane_off + 512 * m;
+      if (j + 8 <= a.cols) {
+        *reinterpret_cast<uint4*>(row + j) =
+            make_uint4(wide[d][m][0], wide[d][m][1], wide[d][m][2], wide[d][m][3]);
+        *reinterpret_cast<uint4*>(row + j + 4) =
+            make_uint4(wide[d][m][4], wide[d][m][5], wide[d][m][6], wide[d][m][7]);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          if (j + k < a.cols) row[j + k] = wide[d][m][k];
+      }
+    }
+  }
+}
+
+// Grid form: one workgroup per tile of one job, ordered DM-tile-major with a
+// contiguous run of tiles per XCD (workgroups go to the 8 XCDs round-robin).
+template <int D, int M, int WD, int WT, int CS, int NLD>
+__global__ __launch_bounds__(64 * WD * WT) void k_dedisp_lds_u8(LdsArgs a) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+  const int32_t nblk = a.n_dtiles * a.n_ttiles;
+  const int32_t b = blockIdx.x;
+  const int32_t full = nblk & ~7;
+  const int32_t L = b < full ? (b & 7) * (full >> 3) + (b >> 3) : b;
+  const int32_t dtile = L / a.n_ttiles;
+  dd_tile<D, M, WD, WT, CS, NLD>(a, dtile, L - dtile * a.n_ttiles, lds);
+}
+
+// Persistent form for a batch of jobs (beams x DM ranges with the same tile
+// shape): the global tile list (job by job, DM-tile-major inside a job) is
+// cut into 8 contiguous parts, one per XCD; the workgroups of an XCD take
+// the tiles of its part in order from an atomic counter until it runs dry.
+template <int D, int M, int WD, int WT, int CS, int NLD>
+__global__ __launch_bounds__(64 * WD * WT) void k_dedisp_lds_multi(MultiArgs m) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+  __shared__ int32_t s_tile;
+  const int32_t total = m.tile_base[m.njobs];
+  const int xcd = blockIdx.x & 7;
+  const int32_t lo = (int32_t)(((int64_t)total * xcd) >> 3);
+  const int32_t hi = (int32_t)(((int64_t)total * (xcd + 1)) >> 3);
+  for (;;) {
+    if (threadIdx.x == 0) s_tile = lo + (int32_t)atomicAdd(&m.counters[xcd], 1u);
+    __syncthreads();
+    const int32_t t = s_tile;
+    __syncthreads();
+    if (t >= hi) break;
+    int j = 0;
+    while (j + 1 < m.njobs && t >= m.tile_base[j + 1]) ++j;
+    const LdsArgs a = m.jobs[j];
+    const int32_t L = t - m.tile_base[j];
+    const int32_t dtile = L / a.n_ttiles;
+    dd_tile<D, M, WD, WT, CS, NLD>(a, dtile, L - dtile * a.n_ttiles, lds);
+  }
+}
+
+__global__ void k_zero_counters(uint32_t* c) {
+  if (threadIdx.x < 8) c[threadIdx.x] = 0u;
+}
+
+template <int D, int M, int WD, int WT, int CS, int NLD>
+hipError_t launch_multi(const MultiArgs& m, int32_t max_win, hipStream_t s) {
+  constexpr int NT = 64 * WD * WT;
+  const size_t lds = (size_t)2 * CS * 2 * max_win;
+  auto kern = k_dedisp_lds_multi<D, M, WD, WT, CS, NLD>;
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  int per_cu = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, NT, lds);
+  if (e != hipSuccess) return e;
+  int dev = 0, ncu = 0;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+  if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+    return e;
+  int nblk = (per_cu < 1 ? 1 : per_cu) * ncu;
+  nblk = (nblk + 7) / 8 * 8;
+  hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, s, m.counters);
+  hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(NT), lds, s, m);
+  return hipGetLastError();
+}
+
+template <int D, int M, int WD, int WT, int CS, int NLD>
+hipError_t launch_one(const LdsArgs& a, hipStream_t s) {
+  constexpr int NT = 64 * WD * WT;
+  const size_t lds = (size_t)2 * CS * 2 * a.win;
+  auto kern = k_dedisp_lds_u8<D, M, WD, WT, CS, NLD>;
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  const unsigned nblk = (unsigned)(a.n_dtiles * a.n_ttiles);
+  hipLaunchKernelGGL(kern, dim3(nblk), dim3(NT), lds, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+// The built menu, {D, M, WD, WT, CS, NLD}; sdd_tile carries it as
+// {kind 1, D, WD, WT, pairs per lane = 4*M, CS}.
+const LdsShape kLdsShapes[] = {
+    {8, 1, 4, 1, 8, 4},
+    {8, 1, 8, 1, 4, 2},
+    {4, 1, 8, 2, 4, 1},
+    {4, 2, 8, 1, 8, 4},
+    {4, 1, 16, 1, 4, 1},
+};
+const int kNumLdsShapes = sizeof(kLdsShapes) / sizeof(kLdsShapes[0]);
+
+hipError_t launch_dedisperse_lds(const LdsArgs& a, int shape, hipStream_t s) {
+  switch (shape) {
+    case 0: return launch_one<8, 1, 4, 1, 8, 4>(a, s);
+    case 1: return launch_one<8, 1, 8, 1, 4, 2>(a, s);
+    case 2: return launch_one<4, 1, 8, 2, 4, 1>(a, s);
+    case 3: return launch_one<4, 2, 8, 1, 8, 4>(a, s);
+    case 4: return launch_one<4, 1, 16, 1, 4, 1>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_dedisperse_lds_multi(const MultiArgs& m, int32_t max_win, int shape,
+                                       hipStream_t s) {
+  switch (shape) {
+    case 0: return launch_multi<8, 1, 4, 1, 8, 4>(m, max_win, s);
+    case 1: return launch_multi<8, 1, 8, 1, 4, 2>(m, max_win, s);
+    case 2: return launch_multi<4, 1, 8, 2, 4, 1>(m, max_win, s);
+    case 3: return launch_multi<4, 2, 8, 1, 8, 4>(m, max_win, s);
+    case 4: return launch_multi<4, 1, 16, 1, 4, 1>(m, max_win, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace sdd

@@ -14,10 +14,13 @@ constexpr int kCtPad = 4;
 // One workgroup turns a 256-sample x 64-channel tile through LDS: reads are
 // rows of 64 channel bytes per spectrum, writes are rows of 256 sample bytes
 // per channel (one full wavefront of dwords).
+// With ring_rows > 0 the input is a ring of ring_rows spectra and sample t
+// of the window is row (ring_start + t) mod ring_rows.
 __global__ __launch_bounds__(256) void k_corner_turn(const uint8_t* __restrict__ in, int64_t nsamp,
                                                      int64_t in_pitch, int32_t nchan,
                                                      uint8_t* __restrict__ out, int64_t out_pitch,
-                                                     int dword_in, int dword_out) {
+                                                     int dword_in, int dword_out,
+                                                     int64_t ring_rows, int64_t ring_start) {
   __shared__ __attribute__((aligned(16))) uint8_t tile[kCtChan][kCtTime + kCtPad];
   const int tid = threadIdx.x;
   const int32_t c0 = blockIdx.y * kCtChan;
@@ -29,7 +32,12 @@ __global__ __launch_bounds__(256) void k_corner_turn(const uint8_t* __restrict__
     const int64_t t = t0 + r;
     uint32_t v = 0;
     if (t < nsamp) {
-      const uint8_t* src = in + t * in_pitch + c0 + cc;
+      int64_t row = t;
+      if (ring_rows > 0) {
+        row = ring_start + t;
+        row -= (row / ring_rows) * ring_rows;
+      }
+      const uint8_t* src = in + row * in_pitch + c0 + cc;
       if (dword_in && c0 + cc + 3 < nchan) {
         v = *reinterpret_cast<const uint32_t*>(src);
       } else {
@@ -77,12 +85,13 @@ __global__ __launch_bounds__(256) void k_decimate(const Tin* __restrict__ in, in
 }  // namespace
 
 hipError_t launch_corner_turn(const uint8_t* in, int64_t nsamp, int64_t in_pitch, int32_t nchan,
-                              uint8_t* out, int64_t out_pitch, hipStream_t s) {
+                              uint8_t* out, int64_t out_pitch, hipStream_t s, int64_t ring_rows,
+                              int64_t ring_start) {
   const int dword_in = ((uintptr_t)in % 4 == 0) && (in_pitch % 4 == 0);
   const int dword_out = ((uintptr_t)out % 4 == 0) && (out_pitch % 4 == 0);
   dim3 grid((unsigned)((nsamp + kCtTime - 1) / kCtTime), (unsigned)((nchan + kCtChan - 1) / kCtChan));
   hipLaunchKernelGGL(k_corner_turn, grid, dim3(256), 0, s, in, nsamp, in_pitch, nchan, out,
-                     out_pitch, dword_in, dword_out);
+                     out_pitch, dword_in, dword_out, ring_rows, ring_start);
   return hipGetLastError();
 }
 

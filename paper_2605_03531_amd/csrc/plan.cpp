@@ -3,11 +3,13 @@
 // workspace layout. Nothing here launches a kernel; only plan_upload touches
 // the GPU (on first use by a compute call).
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
 
+#include "k_dedisp_lds.h"
 #include "sdd_internal.h"
 
 namespace sdd {
@@ -56,10 +58,28 @@ void clear_error() { g_err[0] = 0; }
 const char* last_error() { return g_err; }
 
 const std::vector<sdd_tile>& tile_menu() {
-  static const std::vector<sdd_tile> menu = {
-      {0, 0, 0, 0, 0, 0},
-  };
+  static const std::vector<sdd_tile> menu = [] {
+    std::vector<sdd_tile> m;
+    for (int k = 0; k < kNumLdsShapes; ++k) {
+      const LdsShape& sh = kLdsShapes[k];
+      m.push_back({1, sh.d, sh.wd, sh.wt, 4 * sh.m, sh.cs});
+    }
+    m.push_back({0, 0, 0, 0, 0, 0});
+    return m;
+  }();
   return menu;
+}
+
+// Index of t in the LDS shape table, or -1.
+int lds_shape_index(const sdd_tile& t) {
+  if (t.kind != 1) return -1;
+  for (int k = 0; k < kNumLdsShapes; ++k) {
+    const LdsShape& sh = kLdsShapes[k];
+    if (t.dm_per_wave == sh.d && t.waves_dm == sh.wd && t.waves_time == sh.wt &&
+        t.pairs_per_lane == 4 * sh.m && t.chan_stage == sh.cs)
+      return k;
+  }
+  return -1;
 }
 
 bool tile_in_menu(const sdd_tile& t) {
@@ -80,17 +100,46 @@ int32_t range_span(const sdd_plan* p, int32_t r, int32_t dm_tile) {
   return span;
 }
 
-sdd_status check_tile_fits(const sdd_plan* p, int32_t r, const sdd_tile& t) {
-  (void)p;
-  (void)r;
+sdd_status check_tile_fits(const sdd_plan* p, int32_t r, const sdd_tile& t, int32_t* span_out) {
   if (!tile_in_menu(t)) SDD_FAIL(SDD_EINVAL, "tile shape not in the built menu");
+  if (span_out) *span_out = 0;
+  if (t.kind == 0) return SDD_OK;
+  const Range& R = p->ranges[r];
+  if (R.dec != 1) SDD_FAIL(SDD_EINVAL, "range %d: the LDS kernel takes 8-bit (undecimated) input", r);
+  // the kernel takes a tile's first trial as its smallest delay
+  for (size_t i = 1; i < R.dms.size(); ++i)
+    if (R.dms[i] < R.dms[i - 1])
+      SDD_FAIL(SDD_EINVAL, "range %d: the LDS kernel needs ascending trial DMs", r);
+  const LdsShape& sh = kLdsShapes[lds_shape_index(t)];
+  const int32_t dt = sh.d * sh.wd, tt = 512 * sh.m * sh.wt, nt = 64 * sh.wd * sh.wt;
+  const int32_t span = range_span(p, r, dt);
+  const int64_t win = lds_window(tt, span);
+  const int64_t lds = 4 * (int64_t)sh.cs * win;
+  if (lds > 160 * 1024)
+    SDD_FAIL(SDD_EINVAL, "range %d: delay span %d needs %lld bytes of LDS for this tile", r, span,
+             (long long)lds);
+  if ((int64_t)sh.cs * (win / 16) > (int64_t)sh.nld * nt)
+    SDD_FAIL(SDD_EINVAL, "range %d: delay span %d exceeds this tile's staging capacity", r, span);
+  if (span_out) *span_out = span;
   return SDD_OK;
 }
 
-sdd_tile default_tile(const sdd_plan* p, int32_t r) {
-  (void)p;
-  (void)r;
-  return tile_menu()[0];
+sdd_tile default_tile(const sdd_plan* p, int32_t r, int32_t* span_out) {
+  // preference order of the LDS shapes, then the direct kernel
+  static const int order[] = {1, 0, 3, 2, 4};
+  for (int k : order) {
+    if (k >= kNumLdsShapes) continue;
+    const LdsShape& sh = kLdsShapes[k];
+    sdd_tile t{1, sh.d, sh.wd, sh.wt, 4 * sh.m, sh.cs};
+    int32_t span = 0;
+    if (check_tile_fits(p, r, t, &span) == SDD_OK) {
+      *span_out = span;
+      return t;
+    }
+  }
+  clear_error();
+  *span_out = 0;
+  return sdd_tile{0, 0, 0, 0, 0, 0};
 }
 
 sdd_status plan_geometry(const sdd_plan* p, int64_t nsamp_in, CallGeom* out) {
@@ -212,7 +261,9 @@ extern "C" sdd_status sdd_plan_create(const sdd_plan_desc* d, sdd_plan** out) {
   if (d->cand_block < 0) SDD_FAIL(SDD_EINVAL, "cand_block must be >= 1 (0 = 1024)");
   if (!std::isfinite(d->threshold)) SDD_FAIL(SDD_EINVAL, "threshold must be finite");
 
+  static std::atomic<uint64_t> next_id{1};
   sdd_plan* p = new sdd_plan();
+  p->id = next_id.fetch_add(1);
   p->nchan = d->nchan;
   p->layout = d->layout;
   p->device = d->device;
@@ -297,7 +348,8 @@ extern "C" sdd_status sdd_plan_create(const sdd_plan_desc* d, sdd_plan** out) {
   for (const auto& R : p->ranges)
     O = std::max<int64_t>(O, ((int64_t)R.max_delay + p->w_max - 1) * R.dec);
   p->overlap = O;
-  for (size_t r = 0; r < p->ranges.size(); ++r) p->ranges[r].tile = default_tile(p, (int32_t)r);
+  for (size_t r = 0; r < p->ranges.size(); ++r)
+    p->ranges[r].tile = default_tile(p, (int32_t)r, &p->ranges[r].tile_span);
   *out = p;
   return SDD_OK;
 }
@@ -378,11 +430,16 @@ extern "C" sdd_status sdd_plan_set_tile(sdd_plan* p, int32_t r, const sdd_tile* 
   if (!p || !t) SDD_FAIL(SDD_EINVAL, "null argument");
   if (r < -1 || r >= (int32_t)p->ranges.size()) SDD_FAIL(SDD_EINVAL, "bad range %d", r);
   int32_t r0 = r < 0 ? 0 : r, r1 = r < 0 ? (int32_t)p->ranges.size() : r + 1;
+  std::vector<int32_t> spans(r1 - r0);
   for (int32_t k = r0; k < r1; ++k) {
-    sdd_status st = check_tile_fits(p, k, *t);
+    sdd_status st = check_tile_fits(p, k, *t, &spans[k - r0]);
     if (st != SDD_OK) return st;
   }
-  for (int32_t k = r0; k < r1; ++k) p->ranges[k].tile = *t;
+  for (int32_t k = r0; k < r1; ++k) {
+    p->ranges[k].tile = *t;
+    p->ranges[k].tile_span = spans[k - r0];
+  }
+  p->version++;
   return SDD_OK;
 }
 

@@ -33,6 +33,8 @@ void drain_locked() {
 StageTimer::StageTimer(int stage, hipStream_t s) : stage_(stage), s_(s) {
   std::lock_guard<std::mutex> lk(g_mu);
   if (!g_on) return;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s_, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
   if (hipEventCreate(&a_) != hipSuccess) return;
   if (hipEventCreate(&b_) != hipSuccess) {
     (void)hipEventDestroy(a_);

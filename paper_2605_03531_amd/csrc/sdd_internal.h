@@ -58,6 +58,7 @@ struct Range {
   int32_t max_delay = 0;
   int32_t dm_offset = 0;
   sdd_tile tile{};
+  int32_t tile_span = 0;  // largest delay difference inside one DM tile of `tile`
   int32_t ndm() const { return (int32_t)dms.size(); }
 };
 
@@ -99,6 +100,9 @@ struct sdd_plan {
   int32_t ndm_total = 0;
   int32_t dec_max = 1;
 
+  uint64_t id = 0;       // process-unique, never reused
+  uint64_t version = 0;  // bumped whenever the tile choice changes
+
   // device copies, made on first use
   mutable std::mutex mu;
   mutable int uploaded_device = -1;
@@ -119,13 +123,21 @@ const std::vector<sdd_tile>& tile_menu();
 // Largest delay difference across any DM tile of dm_tile consecutive trials of
 // range r, over all channels (LDS window sizing).
 int32_t range_span(const sdd_plan* p, int32_t r, int32_t dm_tile);
-sdd_status check_tile_fits(const sdd_plan* p, int32_t r, const sdd_tile& t);
-sdd_tile default_tile(const sdd_plan* p, int32_t r);
+// Checks that tile t can run range r; on success *span_out (if given) receives
+// the DM-tile delay span the kernel's LDS window must cover.
+sdd_status check_tile_fits(const sdd_plan* p, int32_t r, const sdd_tile& t,
+                           int32_t* span_out = nullptr);
+sdd_tile default_tile(const sdd_plan* p, int32_t r, int32_t* span_out);
+// LDS window bytes per copy for a tile of TT samples and the given span.
+inline int32_t lds_window(int32_t tt, int32_t span) { return (tt + span + 32 + 15) / 16 * 16; }
 
 // ---- kernel launchers (k_*.hip) ----------------------------------------
 
+// ring_rows > 0: `in` is a ring of ring_rows spectra and the window starts at
+// row ring_start (rows wrap modulo ring_rows).
 hipError_t launch_corner_turn(const uint8_t* in, int64_t nsamp, int64_t in_pitch, int32_t nchan,
-                              uint8_t* out, int64_t out_pitch, hipStream_t s);
+                              uint8_t* out, int64_t out_pitch, hipStream_t s,
+                              int64_t ring_rows = 0, int64_t ring_start = 0);
 // out[c][j] = sum_{k<factor} in[c][j*factor+k], j < out_len; in is u8 or u16.
 hipError_t launch_decimate(const void* in, int in_bytes, int64_t in_pitch, int32_t nchan,
                            int32_t factor, uint16_t* out, int64_t out_pitch, int64_t out_len,
@@ -177,5 +189,60 @@ struct SearchArgs {
   int32_t* ncand;
 };
 hipError_t launch_search(const SearchArgs& a, hipStream_t s);
+
+// ---- one chunk's launch sequence (capi.cpp) -------------------------------
+
+// Corner turn and decimations of one chunk; appends one dedispersion job per
+// DM range (not launched).
+sdd_status prep_item(const sdd_plan* p, const CallGeom& cg, const uint8_t* d_in, int64_t nsamp_in,
+                     int64_t in_pitch, uint32_t* const* planes, const int64_t* pitch, uint8_t* ws,
+                     hipStream_t s, std::vector<DedispArgs>* jobs, int64_t ring_rows = 0,
+                     int64_t ring_start = 0);
+sdd_status run_dedisperse(const sdd_plan* p, const CallGeom& cg, const uint8_t* d_in,
+                          int64_t nsamp_in, int64_t in_pitch, uint32_t* const* planes,
+                          const int64_t* pitch, uint8_t* ws, hipStream_t s);
+sdd_status run_search(const sdd_plan* p, const CallGeom& cg, const uint32_t* const* planes,
+                      const int64_t* pitch, sdd_dm_best* best, sdd_dm_stats* stats,
+                      sdd_candidate* cands, int32_t cap, int32_t* ncand, uint8_t* ws,
+                      hipStream_t s);
+sdd_status check_input(const sdd_plan* p, const uint8_t* d_in, int64_t nsamp_in, int64_t in_pitch);
+sdd_status check_planes(const sdd_plan* p, const CallGeom& cg, const void* const* planes,
+                        const int64_t* pitch);
+// Dedispersion of a set of jobs: jobs sharing an LDS tile shape go through the
+// persistent multi-job kernel; the rest are launched one by one.
+sdd_status launch_jobs_persistent(const std::vector<DedispArgs>& jobs, uint32_t* counters,
+                                  hipStream_t s);
+
+// ---- batches (batch.cpp) ------------------------------------------------
+
+constexpr int64_t kCounterBytes = 256;  // per-XCD tile counters at the workspace start
+
+// One chunk of a batch; ring_rows > 0 marks a time-major ring input whose
+// window starts at row ring_start.
+struct BatchJob {
+  sdd_batch_item it;
+  int64_t ring_rows = 0, ring_start = 0;
+};
+struct ItemGeom {
+  CallGeom cg;
+  int64_t ws_off = 0, ws_bytes = 0;
+  uint32_t* planes[SDD_MAX_RANGES];
+  int64_t pitch[SDD_MAX_RANGES];
+};
+sdd_status batch_layout(const BatchJob* items, int32_t n, std::vector<ItemGeom>* out,
+                        int64_t* total);
+sdd_status enqueue_batch(const BatchJob* items, int32_t n, int32_t flags,
+                         std::vector<ItemGeom>& geo, uint8_t* ws, hipStream_t s);
+
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && hipSetDevice(dev) == hipSuccess) ok = true;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
 
 }  // namespace sdd

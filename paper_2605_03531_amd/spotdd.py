@@ -267,3 +267,167 @@ class Plan:
 def plane_host(plane, cols: int) -> np.ndarray:
     """Device int32 plane -> host uint32 [ndm][cols] (the defined columns)."""
     return plane[:, :cols].cpu().numpy().view(np.uint32)
+
+
+class Batch:
+    """A set of chunks (beams) dedispersed and searched in one call
+    (sdd_batch_dedisperse_search). items: list of (plan, x, planes, out);
+    planes may be None (kept in the workspace), out a SearchOut or None for
+    plane-only plans."""
+
+    def __init__(self, items):
+        self._items = list(items)
+        n = len(self._items)
+        self._arr = (A.BatchItem * n)()
+        self._keep = []
+        for k, (plan, x, planes, out) in enumerate(self._items):
+            nsamp, pitch = plan._input(x)
+            it = self._arr[k]
+            it.plan = plan.handle
+            it.d_in = x.data_ptr()
+            it.nsamp_in = nsamp
+            it.in_pitch = pitch
+            if planes is not None:
+                ptrs, pp = plan._planes(planes)
+                self._keep += [ptrs, pp]
+                it.d_planes = C.cast(ptrs, C.POINTER(C.c_void_p))
+                it.plane_pitch = C.cast(pp, C.POINTER(C.c_int64))
+            if out is not None:
+                it.d_best = out.best.data_ptr()
+                it.d_stats = out.stats.data_ptr()
+                it.d_cands = out.cands.data_ptr()
+                it.cap = out.cands.numel() // CAND_DTYPE.itemsize
+                it.d_ncand = out.ncand.data_ptr()
+        self.device = self._items[0][0].device
+
+    def workspace_bytes(self) -> int:
+        b = C.c_int64()
+        A.check(A.lib().sdd_batch_workspace_size(self._arr, len(self._items), C.byref(b)),
+                "sdd_batch_workspace_size")
+        return b.value
+
+    def workspace(self):
+        torch = _torch()
+        return torch.empty(self.workspace_bytes(), dtype=torch.uint8,
+                           device=f"cuda:{self.device}")
+
+    def run(self, workspace=None, per_item: bool = False, graph: bool = False, stream=None):
+        if workspace is None:
+            workspace = self.workspace()
+        flags = (A.SDD_BATCH_PER_ITEM if per_item else 0) | (A.SDD_BATCH_GRAPH if graph else 0)
+        A.check(A.lib().sdd_batch_dedisperse_search(self._arr, len(self._items), flags,
+                                                    workspace.data_ptr(), workspace.numel(),
+                                                    _stream_handle(stream, self.device)),
+                "sdd_batch_dedisperse_search")
+        return workspace
+
+
+class Stream:
+    """One beam of a Server (sdd_stream)."""
+
+    def __init__(self, server, plan, chunk_nsamp: int, tag: int):
+        self.server, self.plan, self.n, self.tag = server, plan, int(chunk_nsamp), int(tag)
+        h = C.c_void_p()
+        A.check(A.lib().sdd_stream_open(server.handle, plan.handle, self.n, self.tag,
+                                        C.byref(h)), "sdd_stream_open")
+        self._h = h
+        self.seq = 0
+
+    def submit(self, chunk, seq: Optional[int] = None) -> int:
+        """Copies chunk ([n][nchan] uint8 spectra: torch tensor on the device,
+        or a host array) into the ring. Returns the status code: 0, or
+        SDD_EAGAIN (ring full, poll and retry); raises on other errors."""
+        seq = self.seq if seq is None else int(seq)
+        if chunk is None:  # only meaningful for a server in fake mode
+            ptr, dev = None, 0
+        elif hasattr(chunk, "data_ptr"):
+            ptr, dev = chunk.data_ptr(), int(chunk.is_cuda)
+        else:
+            arr = np.ascontiguousarray(chunk, dtype=np.uint8)
+            ptr, dev = arr.ctypes.data, 0
+        st = A.lib().sdd_stream_submit(self._h, ptr, self.n, seq, dev)
+        if st == A.SDD_EAGAIN:
+            return st
+        A.check(st, "sdd_stream_submit")
+        self.seq = seq + 1
+        return st
+
+    def close(self) -> None:
+        if self._h is not None:
+            A.check(A.lib().sdd_stream_close(self._h), "sdd_stream_close")
+            self._h = None
+
+
+class Server:
+    """sdd_server: continuous batching of many beams on one GPU."""
+
+    def __init__(self, hbm_budget: int, device: int = 0, max_beams: int = 256,
+                 nstreams: int = 2, max_batch: int = 8, ring_chunks: int = 2, cap: int = 1024,
+                 per_item: bool = False, fake_exec_us: Optional[int] = None):
+        d = A.ServerDesc()
+        d.hbm_budget = int(hbm_budget)
+        d.device = int(device)
+        d.max_beams = int(max_beams)
+        d.nstreams = int(nstreams)
+        d.max_batch = int(max_batch)
+        d.ring_chunks = int(ring_chunks)
+        d.cap = int(cap)
+        d.batch_flags = A.SDD_BATCH_PER_ITEM if per_item else 0
+        if fake_exec_us is not None:
+            d.flags = A.SDD_SERVER_FAKE
+            d.fake_exec_us = int(fake_exec_us)
+        h = C.c_void_p()
+        A.check(A.lib().sdd_server_create(C.byref(d), C.byref(h)), "sdd_server_create")
+        self._h = h
+        self.cap = d.cap
+
+    @property
+    def handle(self):
+        return self._h
+
+    def open(self, plan, chunk_nsamp: int, tag: int = 0) -> Stream:
+        return Stream(self, plan, chunk_nsamp, tag)
+
+    def footprint(self, plan, chunk_nsamp: int) -> int:
+        b = C.c_int64()
+        A.check(A.lib().sdd_stream_footprint(self._h, plan.handle, int(chunk_nsamp),
+                                             C.byref(b)), "sdd_stream_footprint")
+        return b.value
+
+    def poll(self, max_results: int = 64, timeout_us: int = 0) -> list:
+        """Finished results as dicts (host copies; released at once)."""
+        arr = (A.Result * max_results)()
+        n = C.c_int32()
+        st = A.lib().sdd_stream_poll(self._h, arr, max_results, int(timeout_us), C.byref(n))
+        if st == A.SDD_ETIMEDOUT:
+            return []
+        A.check(st, "sdd_stream_poll")
+        out = []
+        for k in range(n.value):
+            r = arr[k]
+            nb = r.ndm
+            best = np.frombuffer(C.string_at(r.best, nb * BEST_DTYPE.itemsize), dtype=BEST_DTYPE)
+            nc = min(r.ncand, self.cap)
+            cands = np.frombuffer(C.string_at(r.cands, nc * CAND_DTYPE.itemsize) if nc else b"",
+                                  dtype=CAND_DTYPE)
+            out.append({"tag": r.tag, "chunk": r.chunk, "status": r.status, "ncand": r.ncand,
+                        "best": best.copy(), "cands": cands.copy(), "t_ready_ns": r.t_ready_ns,
+                        "t_start_ns": r.t_start_ns, "t_done_ns": r.t_done_ns})
+            A.check(A.lib().sdd_result_release(self._h, C.byref(r)), "sdd_result_release")
+        return out
+
+    def stats(self) -> dict:
+        s = A.ServerStats()
+        A.check(A.lib().sdd_server_query(self._h, C.byref(s)), "sdd_server_query")
+        return {k: getattr(s, k) for k, _ in A.ServerStats._fields_}
+
+    def close(self) -> None:
+        if self._h is not None:
+            A.lib().sdd_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -178,3 +178,58 @@ def test_edge_constant_input_and_candidate_cap():
     assert capped[2].tobytes() == full[2][:10].tobytes()
     orc = oracle.run(spec2, x)
     compare_search(spec2, full, orc, full_rows=True)
+
+
+def _menu_tiles():
+    import paper_2605_03531_amd as sdd
+    return sdd.tile_menu()
+
+
+def test_every_tile_shape_is_exact():
+    """Each kernel shape of the built menu gives the oracle's plane on a
+    ragged case: 999 channels (odd: the last channel has no partner in its
+    pair), 300 trials (a partial DM tile), a partial time tile and a padded
+    spectra pitch."""
+    f = np.linspace(750.0, 550.0, 999)
+    dms = np.linspace(0.0, 300.0, 300)
+    kw = dict(freqs_mhz=f, t_samp=81.92e-6, dm_list=dms)
+    spec = oracle_plan(kw)
+    T = spec.overlap + 3 * 1024 + 77
+    x = synth.filterbank(31, 999, T, 128.0, 16.0)
+    rows = [0, 1, 63, 64, 150, 255, 256, 298, 299]
+    (_, yo, _), = oracle.run(spec, x, rows=[rows], search=False)
+    plan = _make(kw, "time")
+    seen = []
+    for tile in _menu_tiles():
+        try:
+            plan.set_tile(tile)
+        except Exception:
+            say(f"tile {tile} does not fit this plan")
+            continue
+        say(f"tile {tile}")
+        ph, _, g = gpu_run(plan, x, search=False, time_major=True)
+        assert (ph[0][rows].astype(np.int64) == yo).all(), tile
+        seen.append(ph[0])
+    assert len(seen) >= 3
+    for p in seen[1:]:
+        assert (p == seen[0]).all()
+
+
+def test_lds_tiles_on_channel_major_unaligned_input():
+    """Channel-major input whose row pitch is not a multiple of 16 bytes (the
+    staging falls back to byte loads) is still exact for every LDS shape."""
+    f = np.linspace(500.0, 300.0, 130)
+    dms = np.arange(0.0, 70.0)
+    kw = dict(freqs_mhz=f, t_samp=1.31072e-3, dm_list=dms)
+    spec = oracle_plan(kw)
+    T = spec.overlap + 2000 + 3
+    x = synth.filterbank(32, 130, T, 90.0, 25.0)
+    (_, yo, _), = oracle.run(spec, x, search=False)
+    plan = _make(kw, "chan")
+    for tile in _menu_tiles():
+        try:
+            plan.set_tile(tile)
+        except Exception:
+            continue
+        ph, _, _ = gpu_run(plan, x, search=False)
+        assert (ph[0].astype(np.int64) == yo).all(), tile

@@ -1,0 +1,84 @@
+"""GPU: the streaming server's results equal one-shot calls on the same
+windows (bit for bit), and a beam alone equals the same beam in a mix of
+beams with other channel counts, under a shuffled arrival order."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from _parity import compare_search, oracle_plan, say
+
+pytestmark = pytest.mark.gpu
+
+N = 2048
+CHUNKS = 6
+
+
+def _beam(b, C):
+    f = np.linspace(750.0, 550.0, C)
+    kw = dict(freqs_mhz=f, t_samp=81.92e-6, dm_list=np.linspace(0.0, 80.0, 24 + 8 * b),
+              widths=[1, 2, 4, 8], cand_block=256, threshold=5.0)
+    spec = oracle_plan(kw)
+    T = CHUNKS * N
+    x = synth.filterbank(500 + b, C, T, 120.0, 18.0)
+    d = oracle.delay_table(f, [40.0], 81.92e-6)
+    synth.inject_pulse(x, d[0], 3000 + 100 * b, 3, 40.0)
+    return kw, spec, x
+
+
+def _plan(kw):
+    import paper_2605_03531_amd as sdd
+    return sdd.Plan(kw["freqs_mhz"], kw["t_samp"], dm_list=kw["dm_list"], widths=kw["widths"],
+                    cand_block=kw["cand_block"], threshold=kw["threshold"], layout="time")
+
+
+def _serve(beams, plans, order_seed):
+    import torch
+    import paper_2605_03531_amd as sdd
+    srv = sdd.Server(hbm_budget=8 << 30, nstreams=2, max_batch=4, cap=4096)
+    xs = [torch.from_numpy(synth.to_time_major(x)).to("cuda:0") for _, _, x in beams]
+    streams = [srv.open(p, N, tag=b) for b, p in enumerate(plans)]
+    todo = [(b, k) for b in range(len(beams)) for k in range(CHUNKS)]
+    rng = np.random.Generator(np.random.PCG64(order_seed))
+    rng.shuffle(todo)
+    todo.sort(key=lambda t: t[1])      # per beam in order, beams interleaved randomly
+    res = []
+    for b, k in todo:
+        while streams[b].submit(xs[b][k * N:(k + 1) * N]) != 0:
+            res += srv.poll(16, timeout_us=10000)
+    want = sum((CHUNKS * N - p.overlap) // N for p in plans)
+    t0 = time.time()
+    while len(res) < want and time.time() - t0 < 60:
+        res += srv.poll(64, timeout_us=20000)
+    srv.close()
+    assert len(res) == want
+    return {(r["tag"], r["chunk"]): r for r in res}
+
+
+def test_streamed_results_equal_one_shot_and_alone_equals_mix():
+    import torch
+    beams = [_beam(b, C) for b, C in enumerate([128, 256, 192, 128])]
+    plans = [_plan(kw) for kw, _, _ in beams]
+    say("serving 4 beams")
+    mix = _serve(beams, plans, 11)
+    for b, (kw, spec, x) in enumerate(beams):
+        p = plans[b]
+        for k in range((CHUNKS * N - p.overlap) // N):
+            w = x[:, k * N:k * N + N + p.overlap]
+            xt = torch.from_numpy(synth.to_time_major(w)).to("cuda:0")
+            _, out = p.dedisperse_search(xt, cap=4096)
+            best, stats, cands, n = out.host()
+            r = mix[(b, k)]
+            assert r["status"] == 0 and r["ncand"] == n
+            assert r["best"].tobytes() == best.tobytes(), (b, k)
+            assert r["cands"].tobytes() == cands.tobytes(), (b, k)
+            if k == 1:
+                orc = oracle.run(spec, w, rows=[[0, len(kw["dm_list"]) // 2]])
+                compare_search(spec, (best, stats, cands, n), orc, full_rows=False)
+    say("serving beam 0 alone")
+    alone = _serve(beams[:1], plans[:1], 12)
+    for (tag, k), r in alone.items():
+        assert r["best"].tobytes() == mix[(0, k)]["best"].tobytes()
+        assert r["cands"].tobytes() == mix[(0, k)]["cands"].tobytes()

@@ -1,0 +1,135 @@
+"""Streaming server scheduling, admission and failure handling, on the CPU
+(SDD_SERVER_FAKE: no device memory, batches sleep and yield empty results)."""
+import time
+
+import numpy as np
+import pytest
+
+import paper_2605_03531_amd as sdd
+from paper_2605_03531_amd import _capi as A
+
+
+def _plan(nchan=64, dec_ranges=False):
+    f = np.linspace(750.0, 550.0, nchan)
+    if dec_ranges:
+        return sdd.Plan(f, 81.92e-6, ranges=[(0.0, 10.0, 1.0, 1), (10.0, 20.0, 1.0, 4)],
+                        widths=[1, 2], layout="time")
+    return sdd.Plan(f, 81.92e-6, dm_list=np.linspace(0.0, 50.0, 16), widths=[1, 2, 4],
+                    layout="time")
+
+
+def _drain(srv, want, timeout_s=10.0):
+    got = []
+    t0 = time.time()
+    while len(got) < want and time.time() - t0 < timeout_s:
+        got += srv.poll(64, timeout_us=20000)
+    return got
+
+
+def test_results_for_every_ready_chunk_in_order():
+    p = _plan()
+    N = 1024
+    srv = sdd.Server(hbm_budget=1 << 40, nstreams=2, max_batch=4, fake_exec_us=2000)
+    streams = [srv.open(p, N, tag=10 + b) for b in range(5)]
+    chunks = 6
+    for k in range(chunks):
+        for s in streams:
+            assert s.submit(None) == 0
+    # output chunk k needs (k+1)N + O samples
+    per = (chunks * N - p.overlap) // N
+    res = _drain(srv, per * 5)
+    assert len(res) == per * 5
+    for b in range(5):
+        ks = [r["chunk"] for r in res if r["tag"] == 10 + b]
+        assert ks == list(range(per))
+    st = srv.stats()
+    assert st["chunks"] == per * 5 and st["batches"] < st["chunks"]  # chunks were batched
+    for r in res:
+        assert r["t_ready_ns"] <= r["t_start_ns"] <= r["t_done_ns"]
+    srv.close()
+
+
+def test_admission_by_hbm_footprint_and_beam_limit():
+    p = _plan(nchan=256)
+    N = 4096
+    probe = sdd.Server(hbm_budget=1 << 40, fake_exec_us=10)
+    ring = probe.footprint(p, N)
+    probe.close()
+    assert ring == ((p.overlap + N - 1) // N + 2) * N * 256
+    # budget for the slot buffers and exactly two rings
+    srv = sdd.Server(hbm_budget=1 << 40, max_beams=3, fake_exec_us=10)
+    a = srv.open(p, N)
+    used = srv.stats()["hbm_used"]
+    srv.close()
+    srv = sdd.Server(hbm_budget=used + ring, max_beams=3, fake_exec_us=10)
+    srv.open(p, N)
+    srv.open(p, N)
+    with pytest.raises(sdd.SddError) as ei:
+        srv.open(p, N)
+    assert ei.value.status == A.SDD_EAGAIN
+    srv.close()
+    srv = sdd.Server(hbm_budget=1 << 40, max_beams=2, fake_exec_us=10)
+    srv.open(p, N)
+    srv.open(p, N)
+    with pytest.raises(sdd.SddError) as ei:
+        srv.open(p, N)
+    assert ei.value.status == A.SDD_EAGAIN
+    srv.close()
+
+
+def test_backpressure_sequence_gap_and_bad_chunks():
+    p = _plan()
+    N = 1024
+    srv = sdd.Server(hbm_budget=1 << 40, nstreams=1, max_batch=1, ring_chunks=2,
+                     fake_exec_us=200000)
+    s = srv.open(p, N)
+    rc = [s.submit(None) for _ in range(12)]
+    assert A.SDD_EAGAIN in rc  # ring full while the slow batch holds its chunk
+    k = rc.index(A.SDD_EAGAIN)
+    assert all(r == 0 for r in rc[:k])
+    with pytest.raises(sdd.SddError) as ei:
+        s.submit(None, seq=s.seq + 5)
+    assert ei.value.status == A.SDD_ESTATE
+    with pytest.raises(sdd.SddError) as ei:
+        A.check(A.lib().sdd_stream_submit(s._h, None, N + 1, s.seq, 0), "submit")
+    assert ei.value.status == A.SDD_EINVAL
+    # results free ring slots again
+    assert _drain(srv, 1, 5.0)
+    t0 = time.time()
+    while s.submit(None) == A.SDD_EAGAIN and time.time() - t0 < 5:
+        srv.poll(8, timeout_us=10000)
+    srv.close()
+
+
+def test_poll_timeout_and_close_mid_flight():
+    p = _plan(dec_ranges=True)
+    N = 1024
+    srv = sdd.Server(hbm_budget=1 << 40, nstreams=1, max_batch=2, fake_exec_us=100000)
+    t0 = time.time()
+    assert srv.poll(4, timeout_us=50000) == []
+    assert time.time() - t0 >= 0.04
+    s = srv.open(p, N)
+    for _ in range((p.overlap + N - 1) // N + 2):
+        assert s.submit(None) == 0
+    time.sleep(0.02)           # a batch is now in flight
+    s.close()                  # waits for it, drops the rest
+    res = _drain(srv, 1, 2.0)
+    assert 1 <= len(res) <= 2 and srv.stats()["open_streams"] == 0
+    with pytest.raises(sdd.SddError):
+        A.check(A.lib().sdd_stream_open(srv.handle, _plan(dec_ranges=True).handle, N + 1, 0,
+                                        A.C.byref(A.C.c_void_p())), "open")
+    srv.close()
+
+
+def test_stream_rejects_channel_major_plans_and_bad_desc():
+    f = np.linspace(750.0, 550.0, 8)
+    p = sdd.Plan(f, 81.92e-6, dm_list=[0.0, 1.0], widths=[1], layout="chan")
+    srv = sdd.Server(hbm_budget=1 << 30, fake_exec_us=10)
+    with pytest.raises(sdd.SddError) as ei:
+        srv.open(p, 1024)
+    assert ei.value.status == A.SDD_EINVAL
+    srv.close()
+    with pytest.raises(sdd.SddError):
+        sdd.Server(hbm_budget=0, fake_exec_us=10)
+    with pytest.raises(sdd.SddError):
+        sdd.Server(hbm_budget=1 << 30, nstreams=0, fake_exec_us=10)
