@@ -324,6 +324,10 @@ const LdsShape kLdsShapes[] = {
     {4, 1, 8, 2, 4, 1},
     {4, 2, 8, 1, 8, 4},
     {4, 1, 16, 1, 4, 1},
+    {4, 1, 8, 2, 8, 2},
+    {4, 1, 8, 2, 16, 3},
+    {4, 1, 16, 1, 8, 2},
+    {4, 1, 4, 4, 8, 2},
 };
 const int kNumLdsShapes = sizeof(kLdsShapes) / sizeof(kLdsShapes[0]);
 
@@ -334,6 +338,10 @@ hipError_t launch_dedisperse_lds(const LdsArgs& a, int shape, hipStream_t s) {
     case 2: return launch_one<4, 1, 8, 2, 4, 1>(a, s);
     case 3: return launch_one<4, 2, 8, 1, 8, 4>(a, s);
     case 4: return launch_one<4, 1, 16, 1, 4, 1>(a, s);
+    case 5: return launch_one<4, 1, 8, 2, 8, 2>(a, s);
+    case 6: return launch_one<4, 1, 8, 2, 16, 3>(a, s);
+    case 7: return launch_one<4, 1, 16, 1, 8, 2>(a, s);
+    case 8: return launch_one<4, 1, 4, 4, 8, 2>(a, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -346,6 +354,10 @@ hipError_t launch_dedisperse_lds_multi(const MultiArgs& m, int32_t max_win, int 
     case 2: return launch_multi<4, 1, 8, 2, 4, 1>(m, max_win, s);
     case 3: return launch_multi<4, 2, 8, 1, 8, 4>(m, max_win, s);
     case 4: return launch_multi<4, 1, 16, 1, 4, 1>(m, max_win, s);
+    case 5: return launch_multi<4, 1, 8, 2, 8, 2>(m, max_win, s);
+    case 6: return launch_multi<4, 1, 8, 2, 16, 3>(m, max_win, s);
+    case 7: return launch_multi<4, 1, 16, 1, 8, 2>(m, max_win, s);
+    case 8: return launch_multi<4, 1, 4, 4, 8, 2>(m, max_win, s);
     default: return hipErrorInvalidValue;
   }
 }

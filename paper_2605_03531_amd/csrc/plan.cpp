@@ -126,7 +126,7 @@ sdd_status check_tile_fits(const sdd_plan* p, int32_t r, const sdd_tile& t, int3
 
 sdd_tile default_tile(const sdd_plan* p, int32_t r, int32_t* span_out) {
   // preference order of the LDS shapes, then the direct kernel
-  static const int order[] = {1, 0, 3, 2, 4};
+  static const int order[] = {2, 4, 5, 7, 6, 8, 1, 0, 3};
   for (int k : order) {
     if (k >= kNumLdsShapes) continue;
     const LdsShape& sh = kLdsShapes[k];
