@@ -148,7 +148,9 @@ typedef struct sdd_dm_stats {  /* moments of the owned samples of one trial */
 
 /* Tile shape of the dedispersion kernel (a fixed menu; see sdd_tile_menu).
  * kind 0: direct kernel (one thread per DM and 4 samples, no LDS);
- * kind 1: LDS-tiled kernel. The other fields apply to kind 1. */
+ * kind 1..4: LDS-tiled kernel, 1 + variant flags (1: LDS stages prefetched
+ * two ahead, 2: two 64-bit LDS reads per 8 samples instead of 64 + 32 bits).
+ * The other fields apply to the LDS kernel. */
 typedef struct sdd_tile {
   int32_t kind;
   int32_t dm_per_wave;     /* DM trials per wavefront */
@@ -195,6 +197,13 @@ sdd_status sdd_plan_get_tile(const sdd_plan* plan, int32_t range, sdd_tile* out)
 sdd_status sdd_plan_set_tile(sdd_plan* plan, int32_t range, const sdd_tile* tile);
 /* Writes up to max menu entries to host_out; *n_out = menu size. */
 sdd_status sdd_tile_menu(sdd_tile* host_out, int32_t max, int32_t* n_out);
+/* Picks each 8-bit DM range's tile by timing every fitting menu shape on the
+ * device with synthetic input of nsamp_in samples (enqueued on stream, then
+ * synchronised). cache_path (may be NULL) is a text file of earlier choices
+ * keyed by (nchan, ndm, decimation, delay spans, plane width): a hit skips the
+ * timing, a miss appends the new choice. Allocates temporary device buffers
+ * (input and one plane). Results never depend on the tile. */
+sdd_status sdd_autotune(sdd_plan* plan, int64_t nsamp_in, const char* cache_path, void* stream);
 
 /* ---- compute (enqueue on stream) ---------------------------------------- */
 

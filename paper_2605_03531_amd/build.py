@@ -30,9 +30,9 @@ COMMON = [
 
 def _compile(src: str) -> str:
     obj = os.path.join(OBJ, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *COMMON, "-c", src, "-o", obj]
-    if src.endswith(".hip"):
-        cmd[1:1] = ["-x", "hip"]
+    # every source is compiled as HIP (host files include the HIP runtime API,
+    # some .cpp files also hold small kernels)
+    cmd = [HIPCC, "-x", "hip", *COMMON, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}\n{r.stderr}")

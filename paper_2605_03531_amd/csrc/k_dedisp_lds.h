@@ -28,6 +28,7 @@ struct LdsShape {
   int wt;     // wavefronts along time
   int cs;     // channels per LDS stage
   int nld;    // 16-byte staging loads per thread per stage
+  int f;      // variant flags: 1 = stages prefetched two ahead, 2 = 2 x 64-bit reads
 };
 
 extern const LdsShape kLdsShapes[];

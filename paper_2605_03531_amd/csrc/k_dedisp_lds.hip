@@ -32,7 +32,7 @@ __device__ __forceinline__ uint32_t sel_pair(uint32_t s) {
 
 // One DT x TT tile of one job. Every thread of the workgroup calls it; it
 // returns after a barrier, so the caller may reuse the LDS at once.
-template <int D, int M, int WD, int WT, int CS, int NLD>
+template <int D, int M, int WD, int WT, int CS, int NLD, int F>
 __device__ __forceinline__ void dd_tile(const LdsArgs a, int32_t dtile, int32_t ttile,
                                         uint8_t* __restrict__ lds) {
   constexpr int NT = 64 * WD * WT;
@@ -74,8 +74,11 @@ __device__ __forceinline__ void dd_tile(const LdsArgs a, int32_t dtile, int32_t 
     }
 
   // ---- staging: global -> registers -> two LDS copies ----
+  constexpr bool PREF2 = (F & 1) != 0;  // prefetch LDS stages two ahead
+  constexpr bool WIDE = (F & 2) != 0;   // 2 x 64-bit reads instead of 64 + 32
   uint4 st[NLD];
-  auto load_stage = [&](int32_t cbase) {
+  uint4 st2[PREF2 ? NLD : 1];
+  auto load_stage = [&](int32_t cbase, uint4 (&dst)[NLD]) {
 #pragma unroll
     for (int k = 0; k < NLD; ++k) {
       const int32_t e = tid + k * NT;
@@ -95,10 +98,10 @@ __device__ __forceinline__ void dd_tile(const LdsArgs a, int32_t dtile, int32_t 
           v = make_uint4(w[0], w[1], w[2], w[3]);
         }
       }
-      st[k] = v;
+      dst[k] = v;
     }
   };
-  auto store_stage = [&](int32_t which) {
+  auto store_stage = [&](int32_t which, const uint4 (&src)[NLD]) {
     uint8_t* base = lds + which * buf;
 #pragma unroll
     for (int k = 0; k < NLD; ++k) {
@@ -108,10 +111,10 @@ __device__ __forceinline__ void dd_tile(const LdsArgs a, int32_t dtile, int32_t 
       if (cs < CS) {
         uint8_t* c0 = base + cs * slot + 16 * q;  // copy 0
         uint8_t* c1 = c0 + win;                   // copy 1: byte j holds window byte j + 4
-        *reinterpret_cast<uint4*>(c0) = st[k];
-        if (q > 0) *reinterpret_cast<uint32_t*>(c1 - 4) = st[k].x;
-        *reinterpret_cast<uint2*>(c1) = make_uint2(st[k].y, st[k].z);
-        *reinterpret_cast<uint32_t*>(c1 + 8) = st[k].w;
+        *reinterpret_cast<uint4*>(c0) = src[k];
+        if (q > 0) *reinterpret_cast<uint32_t*>(c1 - 4) = src[k].x;
+        *reinterpret_cast<uint2*>(c1) = make_uint2(src[k].y, src[k].z);
+        *reinterpret_cast<uint32_t*>(c1 + 8) = src[k].w;
       }
     }
   };
@@ -152,18 +155,40 @@ __device__ __forceinline__ void dd_tile(const LdsArgs a, int32_t dtile, int32_t 
 
   const int32_t nstages = (nchan + CS - 1) / CS;
   const int32_t lane_off = 8 * lane + TW * wt;
-  load_stage(0);
   int32_t dnext[NDV];
+  int32_t dnext2[PREF2 ? NDV : 1];
+  load_stage(0, st);
   load_delays(0, dnext);
-  store_stage(0);
+  store_stage(0, st);
+  if constexpr (PREF2) {
+    if (nstages > 1) {
+      load_stage(CS, st);
+      load_delays(CS, dnext2);
+    }
+  }
   __syncthreads();
   for (int32_t s = 0; s < nstages; ++s) {
     const int32_t cbase = s * CS;
     int32_t dcur[NDV];
 #pragma unroll
     for (int v = 0; v < NDV; ++v) dcur[v] = dnext[v];
-    if (s + 1 < nstages) {
-      load_stage(cbase + CS);
+    if constexpr (PREF2) {
+      // stage s+1 is in st (loaded one stage ago); fetch stage s+2
+      if (s + 2 < nstages) {
+        load_stage(cbase + 2 * CS, st2);
+        int32_t dtmp[NDV];
+        load_delays(cbase + 2 * CS, dtmp);
+#pragma unroll
+        for (int v = 0; v < NDV; ++v) {
+          dnext[v] = dnext2[v];
+          dnext2[v] = dtmp[v];
+        }
+      } else {
+#pragma unroll
+        for (int v = 0; v < NDV; ++v) dnext[v] = dnext2[v];
+      }
+    } else if (s + 1 < nstages) {
+      load_stage(cbase + CS, st);
       load_delays(cbase + CS, dnext);
     }
     const uint8_t* bufp = lds + (s & 1) * buf + lane_off;
@@ -187,9 +212,19 @@ __device__ __forceinline__ void dd_tile(const LdsArgs a, int32_t dtile, int32_t 
           const uint8_t* pA = slotA + adA + 512 * m;
           const uint8_t* pB = slotB + adB + 512 * m;
           const uint2 a01 = *reinterpret_cast<const uint2*>(pA);
-          const uint32_t a2 = *reinterpret_cast<const uint32_t*>(pA + 8);
           const uint2 b01 = *reinterpret_cast<const uint2*>(pB);
-          const uint32_t b2 = *reinterpret_cast<const uint32_t*>(pB + 8);
+          uint32_t a2, b2;
+          if constexpr (WIDE) {
+            const uint2 a23 = *reinterpret_cast<const uint2*>(pA + 8);
+            const uint2 b23 = *reinterpret_cast<const uint2*>(pB + 8);
+            // keep the full 64-bit reads (conflict-free at an 8-byte lane stride)
+            asm volatile("" ::"v"(a23.y), "v"(b23.y));
+            a2 = a23.x;
+            b2 = b23.x;
+          } else {
+            a2 = *reinterpret_cast<const uint32_t*>(pA + 8);
+            b2 = *reinterpret_cast<const uint32_t*>(pB + 8);
+          }
           acc[d][m][0] += __builtin_amdgcn_perm(a01.y, a01.x, sA0) +
                           __builtin_amdgcn_perm(b01.y, b01.x, sB0);
           acc[d][m][1] += __builtin_amdgcn_perm(a01.y, a01.x, sA2) +
@@ -202,7 +237,11 @@ __device__ __forceinline__ void dd_tile(const LdsArgs a, int32_t dtile, int32_t 
       }
     }
     if (((cbase + CS) & 255) == 0 || s + 1 == nstages) flush();
-    if (s + 1 < nstages) store_stage((s + 1) & 1);
+    if (s + 1 < nstages) store_stage((s + 1) & 1, st);
+    if constexpr (PREF2) {
+#pragma unroll
+      for (int k = 0; k < NLD; ++k) st[k] = st2[k];
+    }
     __syncthreads();
   }
 
@@ -233,7 +272,7 @@ __device__ __forceinline__ void dd_tile(const LdsArgs a, int32_t dtile, int32_t 
 
 // Grid form: one workgroup per tile of one job, ordered DM-tile-major with a
 // contiguous run of tiles per XCD (workgroups go to the 8 XCDs round-robin).
-template <int D, int M, int WD, int WT, int CS, int NLD>
+template <int D, int M, int WD, int WT, int CS, int NLD, int F>
 __global__ __launch_bounds__(64 * WD * WT) void k_dedisp_lds_u8(LdsArgs a) {
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
   const int32_t nblk = a.n_dtiles * a.n_ttiles;
@@ -241,14 +280,14 @@ __global__ __launch_bounds__(64 * WD * WT) void k_dedisp_lds_u8(LdsArgs a) {
   const int32_t full = nblk & ~7;
   const int32_t L = b < full ? (b & 7) * (full >> 3) + (b >> 3) : b;
   const int32_t dtile = L / a.n_ttiles;
-  dd_tile<D, M, WD, WT, CS, NLD>(a, dtile, L - dtile * a.n_ttiles, lds);
+  dd_tile<D, M, WD, WT, CS, NLD, F>(a, dtile, L - dtile * a.n_ttiles, lds);
 }
 
 // Persistent form for a batch of jobs (beams x DM ranges with the same tile
 // shape): the global tile list (job by job, DM-tile-major inside a job) is
 // cut into 8 contiguous parts, one per XCD; the workgroups of an XCD take
 // the tiles of its part in order from an atomic counter until it runs dry.
-template <int D, int M, int WD, int WT, int CS, int NLD>
+template <int D, int M, int WD, int WT, int CS, int NLD, int F>
 __global__ __launch_bounds__(64 * WD * WT) void k_dedisp_lds_multi(MultiArgs m) {
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
   __shared__ int32_t s_tile;
@@ -267,7 +306,7 @@ __global__ __launch_bounds__(64 * WD * WT) void k_dedisp_lds_multi(MultiArgs m) 
     const LdsArgs a = m.jobs[j];
     const int32_t L = t - m.tile_base[j];
     const int32_t dtile = L / a.n_ttiles;
-    dd_tile<D, M, WD, WT, CS, NLD>(a, dtile, L - dtile * a.n_ttiles, lds);
+    dd_tile<D, M, WD, WT, CS, NLD, F>(a, dtile, L - dtile * a.n_ttiles, lds);
   }
 }
 
@@ -275,11 +314,11 @@ __global__ void k_zero_counters(uint32_t* c) {
   if (threadIdx.x < 8) c[threadIdx.x] = 0u;
 }
 
-template <int D, int M, int WD, int WT, int CS, int NLD>
+template <int D, int M, int WD, int WT, int CS, int NLD, int F>
 hipError_t launch_multi(const MultiArgs& m, int32_t max_win, hipStream_t s) {
   constexpr int NT = 64 * WD * WT;
   const size_t lds = (size_t)2 * CS * 2 * max_win;
-  auto kern = k_dedisp_lds_multi<D, M, WD, WT, CS, NLD>;
+  auto kern = k_dedisp_lds_multi<D, M, WD, WT, CS, NLD, F>;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -299,11 +338,11 @@ hipError_t launch_multi(const MultiArgs& m, int32_t max_win, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int D, int M, int WD, int WT, int CS, int NLD>
+template <int D, int M, int WD, int WT, int CS, int NLD, int F>
 hipError_t launch_one(const LdsArgs& a, hipStream_t s) {
   constexpr int NT = 64 * WD * WT;
   const size_t lds = (size_t)2 * CS * 2 * a.win;
-  auto kern = k_dedisp_lds_u8<D, M, WD, WT, CS, NLD>;
+  auto kern = k_dedisp_lds_u8<D, M, WD, WT, CS, NLD, F>;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -316,50 +355,41 @@ hipError_t launch_one(const LdsArgs& a, hipStream_t s) {
 
 }  // namespace
 
-// The built menu, {D, M, WD, WT, CS, NLD}; sdd_tile carries it as
-// {kind 1, D, WD, WT, pairs per lane = 4*M, CS}.
-const LdsShape kLdsShapes[] = {
-    {8, 1, 4, 1, 8, 4},
-    {8, 1, 8, 1, 4, 2},
-    {4, 1, 8, 2, 4, 1},
-    {4, 2, 8, 1, 8, 4},
-    {4, 1, 16, 1, 4, 1},
-    {4, 1, 8, 2, 8, 2},
-    {4, 1, 8, 2, 16, 3},
-    {4, 1, 16, 1, 8, 2},
-    {4, 1, 4, 4, 8, 2},
-};
+// The built menu, {D, M, WD, WT, CS, NLD, F}; sdd_tile carries it as
+// {kind 1 + F, D, WD, WT, pairs per lane = 4*M, CS}.
+#define SDD_LDS_SHAPES(X)      \
+  X(4, 1, 8, 2, 4, 1, 0)       \
+  X(4, 1, 8, 2, 4, 1, 1)       \
+  X(4, 1, 8, 2, 4, 1, 2)       \
+  X(4, 1, 8, 2, 4, 1, 3)       \
+  X(4, 1, 16, 1, 4, 1, 0)      \
+  X(4, 1, 16, 1, 4, 1, 3)      \
+  X(8, 1, 8, 1, 4, 2, 0)       \
+  X(8, 1, 4, 1, 8, 4, 0)
+
+#define SDD_SHAPE_ROW(d, m, wd, wt, cs, nld, f) {d, m, wd, wt, cs, nld, f},
+#define SDD_ONE_PTR(d, m, wd, wt, cs, nld, f) &launch_one<d, m, wd, wt, cs, nld, f>,
+#define SDD_MULTI_PTR(d, m, wd, wt, cs, nld, f) &launch_multi<d, m, wd, wt, cs, nld, f>,
+
+const LdsShape kLdsShapes[] = {SDD_LDS_SHAPES(SDD_SHAPE_ROW)};
 const int kNumLdsShapes = sizeof(kLdsShapes) / sizeof(kLdsShapes[0]);
 
+namespace {
+using OneFn = hipError_t (*)(const LdsArgs&, hipStream_t);
+using MultiFn = hipError_t (*)(const MultiArgs&, int32_t, hipStream_t);
+const OneFn kOne[] = {SDD_LDS_SHAPES(SDD_ONE_PTR)};
+const MultiFn kMulti[] = {SDD_LDS_SHAPES(SDD_MULTI_PTR)};
+}  // namespace
+
 hipError_t launch_dedisperse_lds(const LdsArgs& a, int shape, hipStream_t s) {
-  switch (shape) {
-    case 0: return launch_one<8, 1, 4, 1, 8, 4>(a, s);
-    case 1: return launch_one<8, 1, 8, 1, 4, 2>(a, s);
-    case 2: return launch_one<4, 1, 8, 2, 4, 1>(a, s);
-    case 3: return launch_one<4, 2, 8, 1, 8, 4>(a, s);
-    case 4: return launch_one<4, 1, 16, 1, 4, 1>(a, s);
-    case 5: return launch_one<4, 1, 8, 2, 8, 2>(a, s);
-    case 6: return launch_one<4, 1, 8, 2, 16, 3>(a, s);
-    case 7: return launch_one<4, 1, 16, 1, 8, 2>(a, s);
-    case 8: return launch_one<4, 1, 4, 4, 8, 2>(a, s);
-    default: return hipErrorInvalidValue;
-  }
+  if (shape < 0 || shape >= kNumLdsShapes) return hipErrorInvalidValue;
+  return kOne[shape](a, s);
 }
 
 hipError_t launch_dedisperse_lds_multi(const MultiArgs& m, int32_t max_win, int shape,
                                        hipStream_t s) {
-  switch (shape) {
-    case 0: return launch_multi<8, 1, 4, 1, 8, 4>(m, max_win, s);
-    case 1: return launch_multi<8, 1, 8, 1, 4, 2>(m, max_win, s);
-    case 2: return launch_multi<4, 1, 8, 2, 4, 1>(m, max_win, s);
-    case 3: return launch_multi<4, 2, 8, 1, 8, 4>(m, max_win, s);
-    case 4: return launch_multi<4, 1, 16, 1, 4, 1>(m, max_win, s);
-    case 5: return launch_multi<4, 1, 8, 2, 8, 2>(m, max_win, s);
-    case 6: return launch_multi<4, 1, 8, 2, 16, 3>(m, max_win, s);
-    case 7: return launch_multi<4, 1, 16, 1, 8, 2>(m, max_win, s);
-    case 8: return launch_multi<4, 1, 4, 4, 8, 2>(m, max_win, s);
-    default: return hipErrorInvalidValue;
-  }
+  if (shape < 0 || shape >= kNumLdsShapes) return hipErrorInvalidValue;
+  return kMulti[shape](m, max_win, s);
 }
 
 }  // namespace sdd

@@ -62,7 +62,7 @@ const std::vector<sdd_tile>& tile_menu() {
     std::vector<sdd_tile> m;
     for (int k = 0; k < kNumLdsShapes; ++k) {
       const LdsShape& sh = kLdsShapes[k];
-      m.push_back({1, sh.d, sh.wd, sh.wt, 4 * sh.m, sh.cs});
+      m.push_back({1 + sh.f, sh.d, sh.wd, sh.wt, 4 * sh.m, sh.cs});
     }
     m.push_back({0, 0, 0, 0, 0, 0});
     return m;
@@ -72,10 +72,10 @@ const std::vector<sdd_tile>& tile_menu() {
 
 // Index of t in the LDS shape table, or -1.
 int lds_shape_index(const sdd_tile& t) {
-  if (t.kind != 1) return -1;
+  if (t.kind < 1) return -1;
   for (int k = 0; k < kNumLdsShapes; ++k) {
     const LdsShape& sh = kLdsShapes[k];
-    if (t.dm_per_wave == sh.d && t.waves_dm == sh.wd && t.waves_time == sh.wt &&
+    if (t.kind == 1 + sh.f && t.dm_per_wave == sh.d && t.waves_dm == sh.wd && t.waves_time == sh.wt &&
         t.pairs_per_lane == 4 * sh.m && t.chan_stage == sh.cs)
       return k;
   }
@@ -104,6 +104,7 @@ sdd_status check_tile_fits(const sdd_plan* p, int32_t r, const sdd_tile& t, int3
   if (!tile_in_menu(t)) SDD_FAIL(SDD_EINVAL, "tile shape not in the built menu");
   if (span_out) *span_out = 0;
   if (t.kind == 0) return SDD_OK;
+  if (lds_shape_index(t) < 0) SDD_FAIL(SDD_EINVAL, "tile shape not in the built menu");
   const Range& R = p->ranges[r];
   if (R.dec != 1) SDD_FAIL(SDD_EINVAL, "range %d: the LDS kernel takes 8-bit (undecimated) input", r);
   // the kernel takes a tile's first trial as its smallest delay
@@ -125,12 +126,11 @@ sdd_status check_tile_fits(const sdd_plan* p, int32_t r, const sdd_tile& t, int3
 }
 
 sdd_tile default_tile(const sdd_plan* p, int32_t r, int32_t* span_out) {
-  // preference order of the LDS shapes, then the direct kernel
-  static const int order[] = {2, 4, 5, 7, 6, 8, 1, 0, 3};
-  for (int k : order) {
-    if (k >= kNumLdsShapes) continue;
+  // the first LDS shape of the menu that fits (the menu is in preference
+  // order), else the direct kernel
+  for (int k = 0; k < kNumLdsShapes; ++k) {
     const LdsShape& sh = kLdsShapes[k];
-    sdd_tile t{1, sh.d, sh.wd, sh.wt, 4 * sh.m, sh.cs};
+    sdd_tile t{1 + sh.f, sh.d, sh.wd, sh.wt, 4 * sh.m, sh.cs};
     int32_t span = 0;
     if (check_tile_fits(p, r, t, &span) == SDD_OK) {
       *span_out = span;

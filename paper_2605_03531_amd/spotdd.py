@@ -167,6 +167,12 @@ class Plan:
         t = A.Tile(*[int(v) for v in tile])
         A.check(A.lib().sdd_plan_set_tile(self._p, r, C.byref(t)), "sdd_plan_set_tile")
 
+    def autotune(self, nsamp_in: int, cache_path: Optional[str] = None, stream=None) -> None:
+        """Times the fitting tile shapes on the device and keeps the fastest."""
+        path = cache_path.encode() if cache_path else None
+        A.check(A.lib().sdd_autotune(self._p, int(nsamp_in), path,
+                                     _stream_handle(stream, self.device)), "sdd_autotune")
+
     # -- device buffers -----------------------------------------------
     def workspace(self, nsamp_in: int, with_planes: bool = False):
         torch = _torch()
