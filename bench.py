@@ -73,6 +73,93 @@ def cpu_baseline(w, plan_delays, rows: int):
                       f"({os.cpu_count()} logical CPUs)"}
 
 
+def serve_bench(sdd, torch, nbeams: int, sat_chunks: int, rt_periods: int, max_batch: int,
+                nstreams: int):
+    """Streaming server with nbeams beams (1024/2048/4096 channels by beam
+    index mod 3), 2^16-sample chunks, 2048 DM trials 0-1000, widths 1..64.
+
+    Saturated run: every beam submits sat_chunks chunks as fast as the rings
+    allow; capacity = beams x stream seconds / wall seconds. Real-time run:
+    chunks arrive at the real cadence (5.369 s per chunk) with the beams'
+    phases spread over one period; latency = results on host minus the submit
+    that completed the chunk's input (p50/p99 over the measured periods)."""
+    import synth
+    N = 1 << 16
+    t_samp = 81.92e-6
+    period = N * t_samp
+    chans = [1024, 2048, 4096]
+    dms = np.linspace(0.0, 1000.0, 2048)
+    plans = {C: sdd.Plan(np.linspace(750.0, 550.0, C), t_samp, dm_list=dms, widths=WIDTHS,
+                         cand_block=1024, threshold=7.0, layout="time") for C in chans}
+    pool_n = 3
+    pools = {}
+    for C in chans:
+        x = synth.filterbank(900 + C, C, pool_n * N, 128.0, 16.0)
+        pools[C] = torch.from_numpy(synth.to_time_major(x)).to("cuda:0")
+    beam_c = [chans[b % 3] for b in range(nbeams)]
+
+    def run(chunks_per_beam, realtime, measure_from):
+        srv = sdd.Server(hbm_budget=250 << 30, max_beams=nbeams, nstreams=nstreams,
+                         max_batch=max_batch, ring_chunks=2, cap=4096)
+        streams = [srv.open(plans[beam_c[b]], N, tag=b) for b in range(nbeams)]
+        events = []
+        for b in range(nbeams):
+            phase = (b / nbeams) * period if realtime else 0.0
+            for k in range(chunks_per_beam):
+                events.append((phase + k * period if realtime else k, b, k))
+        events.sort()
+        res = []
+        t0 = time.perf_counter()
+        for when, b, k in events:
+            if realtime:
+                while True:
+                    dt = t0 + when - time.perf_counter()
+                    if dt <= 0:
+                        break
+                    res += srv.poll(256, timeout_us=int(min(dt, 0.05) * 1e6))
+            C = beam_c[b]
+            chunk = pools[C][(k % pool_n) * N:(k % pool_n + 1) * N]
+            while streams[b].submit(chunk) != 0:
+                res += srv.poll(256, timeout_us=2000)
+        want = sum((chunks_per_beam * N - plans[beam_c[b]].overlap) // N for b in range(nbeams))
+        while len(res) < want:
+            got = srv.poll(256, timeout_us=200000)
+            if not got and time.perf_counter() - t0 > 600:
+                break
+            res += got
+        wall = time.perf_counter() - t0
+        stats = srv.stats()
+        srv.close()
+        lat = [(r["t_done_ns"] - r["t_ready_ns"]) * 1e-9 for r in res if r["chunk"] >= measure_from]
+        return res, wall, stats, lat
+
+    log(f"serving: saturated run, {nbeams} beams x {sat_chunks} chunks")
+    res, wall, stats, _ = run(sat_chunks, False, 0)
+    outputs = len(res)
+    stream_s = outputs * period
+    capacity = stream_s / wall  # real-time beams the GPU sustains
+    log(f"serving: {outputs} chunk results in {wall:.2f} s; capacity {capacity:.1f} beams; "
+        f"{stats['batches']} batches")
+    out = {"beams": nbeams, "chunk_samples": N, "chunk_seconds": round(period, 4),
+           "channel_mix": "1024/2048/4096 by beam index mod 3", "ndm": 2048, "widths": WIDTHS,
+           "max_batch": max_batch, "slots": nstreams,
+           "saturated": {"chunks_per_beam": sat_chunks, "results": outputs,
+                         "wall_s": round(wall, 3), "real_time_beams_capacity": round(capacity, 1),
+                         "rtf_per_beam": round(capacity / nbeams, 3)}}
+    if rt_periods > 0:
+        warm = 3  # output chunk k needs input chunks 0..k+2
+        log(f"serving: real-time run, {rt_periods} periods after warm-up")
+        res, wall, stats, lat = run(warm + rt_periods, True, 1)
+        lat = np.array(lat)
+        out["real_time"] = {"periods": warm + rt_periods, "results_measured": int(len(lat)),
+                            "p50_latency_s": round(float(np.percentile(lat, 50)), 4) if len(lat) else None,
+                            "p99_latency_s": round(float(np.percentile(lat, 99)), 4) if len(lat) else None,
+                            "max_latency_s": round(float(lat.max()), 4) if len(lat) else None,
+                            "kept_up": bool(len(lat) and float(np.percentile(lat, 99)) < period)}
+        log(f"serving: p50 {out['real_time']['p50_latency_s']} s, p99 {out['real_time']['p99_latency_s']} s")
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,6 +167,11 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-rows", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true", help="skip the streaming-server run")
+    ap.add_argument("--serve-beams", type=int, default=160)
+    ap.add_argument("--serve-chunks", type=int, default=4, help="chunks per beam, saturated run")
+    ap.add_argument("--serve-periods", type=int, default=2, help="measured real-time periods")
+    ap.add_argument("--serve-batch", type=int, default=16)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: beams shard across GPUs with no exchange, so "
@@ -162,6 +254,12 @@ def main() -> int:
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample")
         res["cpu_baseline"] = cpu_baseline(w, plan.delays(0), args.cpu_rows)
+    res["serving"] = None
+    if not args.no_serve:
+        del xt, planes, ws, out
+        torch.cuda.empty_cache()
+        res["serving"] = serve_bench(sdd, torch, args.serve_beams, args.serve_chunks,
+                                     args.serve_periods, args.serve_batch, 2)
     print(json.dumps(res), flush=True)
     return 0
 

@@ -51,8 +51,11 @@ __global__ __launch_bounds__(256) void k_dedisp_direct(const Tin* __restrict__ x
 int lds_args_for(const DedispArgs& a, LdsArgs* out) {
   const int shape = lds_shape_index(a.tile);
   const bool plane_ok = ((uintptr_t)a.plane % 16 == 0) && (a.plane_pitch % 4 == 0);
-  if (shape < 0 || a.elem_bytes != 1 || !plane_ok || a.cols <= 0 || a.ndm <= 0) return -1;
+  if (shape < 0 || !plane_ok || a.cols <= 0 || a.ndm <= 0) return -1;
   const LdsShape& sh = kLdsShapes[shape];
+  const int es = a.elem_bytes;
+  const int32_t flush = lds_flush_period(sh, a.max_val);
+  if (es < 1 || es > 2 || flush < sh.cs) return -1;
   LdsArgs& l = *out;
   l = LdsArgs{};
   l.x = (const uint8_t*)a.x;
@@ -64,11 +67,13 @@ int lds_args_for(const DedispArgs& a, LdsArgs* out) {
   l.plane = a.plane;
   l.plane_pitch = a.plane_pitch;
   l.cols = a.cols;
-  const int32_t tt = 512 * sh.m * sh.wt, dt = sh.d * sh.wd;
-  l.win = lds_window(tt, a.span);
+  const int32_t tt = lds_tile_samples(sh, es), dt = sh.d * sh.wd;
+  l.win = lds_window_bytes(tt, a.span, es);
   l.n_dtiles = (a.ndm + dt - 1) / dt;
   l.n_ttiles = (int32_t)((a.cols + tt - 1) / tt);
-  l.aligned = ((uintptr_t)a.x % 16 == 0) && (a.x_pitch % 16 == 0);
+  l.aligned = ((uintptr_t)a.x % 16 == 0) && ((a.x_pitch * es) % 16 == 0);
+  l.es = es;
+  l.flush = flush;
   return shape;
 }
 

@@ -6,8 +6,8 @@
 namespace sdd {
 
 struct LdsArgs {
-  const uint8_t* x;       // channel rows, uint8
-  int64_t x_pitch;        // bytes between rows
+  const uint8_t* x;       // channel rows (uint8, or uint16 when es == 2)
+  int64_t x_pitch;        // elements between rows
   int64_t x_len;          // valid samples per row
   int32_t nchan;
   int32_t ndm;
@@ -17,8 +17,11 @@ struct LdsArgs {
   int64_t cols;
   int32_t win;            // LDS window bytes per copy (multiple of 16)
   int32_t n_dtiles, n_ttiles;
-  int32_t aligned;        // x and x_pitch are 16-byte aligned
+  int32_t aligned;        // rows start 16-byte aligned
+  int32_t es;             // element bytes: 1 or 2
+  int32_t flush;          // channels per 16-bit flush (es == 2; multiple of the stage)
 };
+
 
 // Compile-time shape of one instantiation.
 struct LdsShape {
@@ -30,6 +33,15 @@ struct LdsShape {
   int nld;    // 16-byte staging loads per thread per stage
   int f;      // variant flags: 1 = stages prefetched two ahead, 2 = 2 x 64-bit reads
 };
+
+// Samples one tile of a shape covers for elements of es bytes.
+inline int32_t lds_tile_samples(const LdsShape& sh, int es) { return 512 / es * sh.m * sh.wt; }
+// Channels a range of element maximum max_val may add into 16-bit fields
+// before a flush, rounded down to a multiple of the stage (0: not possible).
+inline int32_t lds_flush_period(const LdsShape& sh, int32_t max_val) {
+  const int32_t f = 65535 / max_val;
+  return f >= 256 ? 256 : (f / sh.cs) * sh.cs;
+}
 
 extern const LdsShape kLdsShapes[];
 extern const int kNumLdsShapes;

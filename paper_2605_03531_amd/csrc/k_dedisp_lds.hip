@@ -32,12 +32,23 @@ __device__ __forceinline__ uint32_t sel_pair(uint32_t s) {
 
 // One DT x TT tile of one job. Every thread of the workgroup calls it; it
 // returns after a barrier, so the caller may reuse the LDS at once.
-template <int D, int M, int WD, int WT, int CS, int NLD, int F>
+__device__ __forceinline__ uint32_t sel_quad(uint32_t s) {
+  // bytes s..s+3 of an 8-byte (hi:lo) pair, in order
+  return s | ((s + 1u) << 8) | ((s + 2u) << 16) | ((s + 3u) << 24);
+}
+
+// ES = input element bytes: 1 (uint8 rows) or 2 (uint16 rows of a decimated
+// range). A lane always owns 8 bytes of a 512-byte chunk: 8 uint8 samples
+// (four 16-bit pairs after widening) or 4 uint16 samples (two pairs as read).
+template <int D, int M, int WD, int WT, int CS, int NLD, int F, int ES>
 __device__ __forceinline__ void dd_tile(const LdsArgs a, int32_t dtile, int32_t ttile,
                                         uint8_t* __restrict__ lds) {
   constexpr int NT = 64 * WD * WT;
   constexpr int DT = D * WD;
-  constexpr int TW = 512 * M;   // samples per time group of waves
+  constexpr int SPL = 8 / ES;       // samples per lane per chunk
+  constexpr int CH = 64 * SPL;      // samples per 512-byte chunk
+  constexpr int NPK = SPL / 2;      // packed 16-bit pairs per lane per chunk
+  constexpr int TW = CH * M;        // samples per time group of waves
   constexpr int TT = TW * WT;
   const int32_t i0 = dtile * DT;
   const int64_t t0 = (int64_t)ttile * TT;
@@ -61,16 +72,16 @@ __device__ __forceinline__ void dd_tile(const LdsArgs a, int32_t dtile, int32_t 
   const int32_t buf = CS * slot;
   const int32_t wq = win >> 4;          // 16-byte elements per window
 
-  uint32_t acc[D][M][4];
-  uint32_t wide[D][M][8];
+  uint32_t acc[D][M][NPK];
+  uint32_t wide[D][M][SPL];
 #pragma unroll
   for (int d = 0; d < D; ++d)
 #pragma unroll
     for (int m = 0; m < M; ++m) {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) acc[d][m][k] = 0u;
+      for (int k = 0; k < NPK; ++k) acc[d][m][k] = 0u;
 #pragma unroll
-      for (int k = 0; k < 8; ++k) wide[d][m][k] = 0u;
+      for (int k = 0; k < SPL; ++k) wide[d][m][k] = 0u;
     }
 
   // ---- staging: global -> registers -> two LDS copies ----
@@ -87,14 +98,16 @@ __device__ __forceinline__ void dd_tile(const LdsArgs a, int32_t dtile, int32_t 
       const int32_t c = cbase + cs;
       uint4 v = make_uint4(0u, 0u, 0u, 0u);
       if (cs < CS && c < nchan) {
-        const int64_t g = t0 + (int64_t)(dcm[(int64_t)c * ndm + i0] & ~15) + 16 * q;
-        const uint8_t* src = a.x + (int64_t)c * a.x_pitch + g;
-        if (a.aligned && g + 16 <= a.x_len) {
+        // byte g of channel c's row; the window starts at sample t0 + d(c,i0) & ~15
+        const int64_t g = ES * (t0 + (int64_t)(dcm[(int64_t)c * ndm + i0] & ~15)) + 16 * q;
+        const int64_t row_bytes = ES * a.x_len;
+        const uint8_t* src = a.x + (int64_t)c * a.x_pitch * ES + g;
+        if (a.aligned && g + 16 <= row_bytes) {
           v = *reinterpret_cast<const uint4*>(src);
         } else {
           uint32_t w[4] = {0u, 0u, 0u, 0u};
           for (int bb = 0; bb < 16; ++bb)
-            if (g + bb < a.x_len) w[bb >> 2] |= (uint32_t)src[bb] << (8 * (bb & 3));
+            if (g + bb < row_bytes) w[bb >> 2] |= (uint32_t)src[bb] << (8 * (bb & 3));
           v = make_uint4(w[0], w[1], w[2], w[3]);
         }
       }
@@ -125,7 +138,7 @@ __device__ __forceinline__ void dd_tile(const LdsArgs a, int32_t dtile, int32_t 
 #pragma unroll
       for (int m = 0; m < M; ++m)
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < NPK; ++k) {
           wide[d][m][2 * k] += acc[d][m][k] & 0xffffu;
           wide[d][m][2 * k + 1] += acc[d][m][k] >> 16;
           acc[d][m][k] = 0u;
@@ -154,7 +167,8 @@ __device__ __forceinline__ void dd_tile(const LdsArgs a, int32_t dtile, int32_t 
 #define SDD_DELAY(k) __builtin_amdgcn_readlane(dcur[(k) / 64], (k) % 64)
 
   const int32_t nstages = (nchan + CS - 1) / CS;
-  const int32_t lane_off = 8 * lane + TW * wt;
+  const int32_t lane_off = 8 * lane + ES * TW * wt;  // bytes
+  const int32_t flush_every = ES == 1 ? 256 : a.flush;
   int32_t dnext[NDV];
   int32_t dnext2[PREF2 ? NDV : 1];
   load_stage(0, st);
@@ -200,13 +214,16 @@ __device__ __forceinline__ void dd_tile(const LdsArgs a, int32_t dtile, int32_t 
       const uint8_t* slotB = slotA + slot;
 #pragma unroll
       for (int d = 0; d < D; ++d) {
-        const int32_t oA = SDD_DELAY(cc * DE + 1 + d) - baseA;
-        const int32_t oB = SDD_DELAY((cc + 1) * DE + 1 + d) - baseB;
+        // byte offsets into the windows
+        const int32_t oA = ES * (SDD_DELAY(cc * DE + 1 + d) - baseA);
+        const int32_t oB = ES * (SDD_DELAY((cc + 1) * DE + 1 + d) - baseB);
         // copy 1 when the byte offset within the 8-byte word is >= 4
         const int32_t adA = (oA & ~7) + ((oA & 4) ? win : 0);
         const int32_t adB = (oB & ~7) + ((oB & 4) ? win : 0);
-        const uint32_t sA0 = sel_pair(oA & 3), sA2 = sel_pair((oA & 3) + 2);
-        const uint32_t sB0 = sel_pair(oB & 3), sB2 = sel_pair((oB & 3) + 2);
+        const uint32_t sA0 = ES == 1 ? sel_pair(oA & 3) : sel_quad(oA & 3);
+        const uint32_t sA2 = sel_pair((oA & 3) + 2);
+        const uint32_t sB0 = ES == 1 ? sel_pair(oB & 3) : sel_quad(oB & 3);
+        const uint32_t sB2 = sel_pair((oB & 3) + 2);
 #pragma unroll
         for (int m = 0; m < M; ++m) {
           const uint8_t* pA = slotA + adA + 512 * m;
@@ -225,18 +242,26 @@ __device__ __forceinline__ void dd_tile(const LdsArgs a, int32_t dtile, int32_t 
             a2 = *reinterpret_cast<const uint32_t*>(pA + 8);
             b2 = *reinterpret_cast<const uint32_t*>(pB + 8);
           }
-          acc[d][m][0] += __builtin_amdgcn_perm(a01.y, a01.x, sA0) +
-                          __builtin_amdgcn_perm(b01.y, b01.x, sB0);
-          acc[d][m][1] += __builtin_amdgcn_perm(a01.y, a01.x, sA2) +
-                          __builtin_amdgcn_perm(b01.y, b01.x, sB2);
-          acc[d][m][2] += __builtin_amdgcn_perm(a2, a01.y, sA0) +
-                          __builtin_amdgcn_perm(b2, b01.y, sB0);
-          acc[d][m][3] += __builtin_amdgcn_perm(a2, a01.y, sA2) +
-                          __builtin_amdgcn_perm(b2, b01.y, sB2);
+          if constexpr (ES == 1) {
+            acc[d][m][0] += __builtin_amdgcn_perm(a01.y, a01.x, sA0) +
+                            __builtin_amdgcn_perm(b01.y, b01.x, sB0);
+            acc[d][m][1] += __builtin_amdgcn_perm(a01.y, a01.x, sA2) +
+                            __builtin_amdgcn_perm(b01.y, b01.x, sB2);
+            acc[d][m][2] += __builtin_amdgcn_perm(a2, a01.y, sA0) +
+                            __builtin_amdgcn_perm(b2, b01.y, sB0);
+            acc[d][m][3] += __builtin_amdgcn_perm(a2, a01.y, sA2) +
+                            __builtin_amdgcn_perm(b2, b01.y, sB2);
+          } else {
+            // uint16 samples are already 16-bit fields: v_perm only aligns
+            acc[d][m][0] += __builtin_amdgcn_perm(a01.y, a01.x, sA0) +
+                            __builtin_amdgcn_perm(b01.y, b01.x, sB0);
+            acc[d][m][1] += __builtin_amdgcn_perm(a2, a01.y, sA0) +
+                            __builtin_amdgcn_perm(b2, b01.y, sB0);
+          }
         }
       }
     }
-    if (((cbase + CS) & 255) == 0 || s + 1 == nstages) flush();
+    if ((cbase + CS) % flush_every == 0 || s + 1 == nstages) flush();
     if (s + 1 < nstages) store_stage((s + 1) & 1, st);
     if constexpr (PREF2) {
 #pragma unroll
@@ -255,15 +280,15 @@ __device__ __forceinline__ void dd_tile(const LdsArgs a, int32_t dtile, int32_t 
     uint32_t* row = a.plane + (int64_t)i * a.plane_pitch;
 #pragma unroll
     for (int m = 0; m < M; ++m) {
-      const int64_t j = t0 + lane_off + 512 * m;
-      if (j + 8 <= a.cols) {
-        *reinterpret_cast<uint4*>(row + j) =
-            make_uint4(wide[d][m][0], wide[d][m][1], wide[d][m][2], wide[d][m][3]);
-        *reinterpret_cast<uint4*>(row + j + 4) =
-            make_uint4(wide[d][m][4], wide[d][m][5], wide[d][m][6], wide[d][m][7]);
+      const int64_t j = t0 + TW * wt + CH * m + SPL * lane;
+      if (j + SPL <= a.cols) {
+#pragma unroll
+        for (int k = 0; k < SPL; k += 4)
+          *reinterpret_cast<uint4*>(row + j + k) =
+              make_uint4(wide[d][m][k], wide[d][m][k + 1], wide[d][m][k + 2], wide[d][m][k + 3]);
       } else {
 #pragma unroll
-        for (int k = 0; k < 8; ++k)
+        for (int k = 0; k < SPL; ++k)
           if (j + k < a.cols) row[j + k] = wide[d][m][k];
       }
     }
@@ -272,22 +297,22 @@ __device__ __forceinline__ void dd_tile(const LdsArgs a, int32_t dtile, int32_t 
 
 // Grid form: one workgroup per tile of one job, ordered DM-tile-major with a
 // contiguous run of tiles per XCD (workgroups go to the 8 XCDs round-robin).
-template <int D, int M, int WD, int WT, int CS, int NLD, int F>
-__global__ __launch_bounds__(64 * WD * WT) void k_dedisp_lds_u8(LdsArgs a) {
+template <int D, int M, int WD, int WT, int CS, int NLD, int F, int ES>
+__global__ __launch_bounds__(64 * WD * WT) void k_dedisp_lds(LdsArgs a) {
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
   const int32_t nblk = a.n_dtiles * a.n_ttiles;
   const int32_t b = blockIdx.x;
   const int32_t full = nblk & ~7;
   const int32_t L = b < full ? (b & 7) * (full >> 3) + (b >> 3) : b;
   const int32_t dtile = L / a.n_ttiles;
-  dd_tile<D, M, WD, WT, CS, NLD, F>(a, dtile, L - dtile * a.n_ttiles, lds);
+  dd_tile<D, M, WD, WT, CS, NLD, F, ES>(a, dtile, L - dtile * a.n_ttiles, lds);
 }
 
 // Persistent form for a batch of jobs (beams x DM ranges with the same tile
 // shape): the global tile list (job by job, DM-tile-major inside a job) is
 // cut into 8 contiguous parts, one per XCD; the workgroups of an XCD take
 // the tiles of its part in order from an atomic counter until it runs dry.
-template <int D, int M, int WD, int WT, int CS, int NLD, int F>
+template <int D, int M, int WD, int WT, int CS, int NLD, int F, int ES>
 __global__ __launch_bounds__(64 * WD * WT) void k_dedisp_lds_multi(MultiArgs m) {
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
   __shared__ int32_t s_tile;
@@ -306,7 +331,7 @@ __global__ __launch_bounds__(64 * WD * WT) void k_dedisp_lds_multi(MultiArgs m) 
     const LdsArgs a = m.jobs[j];
     const int32_t L = t - m.tile_base[j];
     const int32_t dtile = L / a.n_ttiles;
-    dd_tile<D, M, WD, WT, CS, NLD, F>(a, dtile, L - dtile * a.n_ttiles, lds);
+    dd_tile<D, M, WD, WT, CS, NLD, F, ES>(a, dtile, L - dtile * a.n_ttiles, lds);
   }
 }
 
@@ -314,11 +339,11 @@ __global__ void k_zero_counters(uint32_t* c) {
   if (threadIdx.x < 8) c[threadIdx.x] = 0u;
 }
 
-template <int D, int M, int WD, int WT, int CS, int NLD, int F>
+template <int D, int M, int WD, int WT, int CS, int NLD, int F, int ES>
 hipError_t launch_multi(const MultiArgs& m, int32_t max_win, hipStream_t s) {
   constexpr int NT = 64 * WD * WT;
   const size_t lds = (size_t)2 * CS * 2 * max_win;
-  auto kern = k_dedisp_lds_multi<D, M, WD, WT, CS, NLD, F>;
+  auto kern = k_dedisp_lds_multi<D, M, WD, WT, CS, NLD, F, ES>;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -338,11 +363,11 @@ hipError_t launch_multi(const MultiArgs& m, int32_t max_win, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int D, int M, int WD, int WT, int CS, int NLD, int F>
+template <int D, int M, int WD, int WT, int CS, int NLD, int F, int ES>
 hipError_t launch_one(const LdsArgs& a, hipStream_t s) {
   constexpr int NT = 64 * WD * WT;
   const size_t lds = (size_t)2 * CS * 2 * a.win;
-  auto kern = k_dedisp_lds_u8<D, M, WD, WT, CS, NLD, F>;
+  auto kern = k_dedisp_lds<D, M, WD, WT, CS, NLD, F, ES>;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -368,8 +393,10 @@ hipError_t launch_one(const LdsArgs& a, hipStream_t s) {
   X(8, 1, 4, 1, 8, 4, 0)
 
 #define SDD_SHAPE_ROW(d, m, wd, wt, cs, nld, f) {d, m, wd, wt, cs, nld, f},
-#define SDD_ONE_PTR(d, m, wd, wt, cs, nld, f) &launch_one<d, m, wd, wt, cs, nld, f>,
-#define SDD_MULTI_PTR(d, m, wd, wt, cs, nld, f) &launch_multi<d, m, wd, wt, cs, nld, f>,
+#define SDD_ONE_PTR(d, m, wd, wt, cs, nld, f) \
+  {&launch_one<d, m, wd, wt, cs, nld, f, 1>, &launch_one<d, m, wd, wt, cs, nld, f, 2>},
+#define SDD_MULTI_PTR(d, m, wd, wt, cs, nld, f) \
+  {&launch_multi<d, m, wd, wt, cs, nld, f, 1>, &launch_multi<d, m, wd, wt, cs, nld, f, 2>},
 
 const LdsShape kLdsShapes[] = {SDD_LDS_SHAPES(SDD_SHAPE_ROW)};
 const int kNumLdsShapes = sizeof(kLdsShapes) / sizeof(kLdsShapes[0]);
@@ -377,19 +404,23 @@ const int kNumLdsShapes = sizeof(kLdsShapes) / sizeof(kLdsShapes[0]);
 namespace {
 using OneFn = hipError_t (*)(const LdsArgs&, hipStream_t);
 using MultiFn = hipError_t (*)(const MultiArgs&, int32_t, hipStream_t);
-const OneFn kOne[] = {SDD_LDS_SHAPES(SDD_ONE_PTR)};
-const MultiFn kMulti[] = {SDD_LDS_SHAPES(SDD_MULTI_PTR)};
+const OneFn kOne[][2] = {SDD_LDS_SHAPES(SDD_ONE_PTR)};
+const MultiFn kMulti[][2] = {SDD_LDS_SHAPES(SDD_MULTI_PTR)};
 }  // namespace
 
 hipError_t launch_dedisperse_lds(const LdsArgs& a, int shape, hipStream_t s) {
-  if (shape < 0 || shape >= kNumLdsShapes) return hipErrorInvalidValue;
-  return kOne[shape](a, s);
+  if (shape < 0 || shape >= kNumLdsShapes || a.es < 1 || a.es > 2) return hipErrorInvalidValue;
+  return kOne[shape][a.es - 1](a, s);
 }
 
 hipError_t launch_dedisperse_lds_multi(const MultiArgs& m, int32_t max_win, int shape,
                                        hipStream_t s) {
-  if (shape < 0 || shape >= kNumLdsShapes) return hipErrorInvalidValue;
-  return kMulti[shape](m, max_win, s);
+  if (shape < 0 || shape >= kNumLdsShapes || m.njobs < 1) return hipErrorInvalidValue;
+  const int es = m.jobs[0].es;
+  for (int j = 1; j < m.njobs; ++j)
+    if (m.jobs[j].es != es) return hipErrorInvalidValue;
+  if (es < 1 || es > 2) return hipErrorInvalidValue;
+  return kMulti[shape][es - 1](m, max_win, s);
 }
 
 }  // namespace sdd

@@ -106,15 +106,18 @@ sdd_status check_tile_fits(const sdd_plan* p, int32_t r, const sdd_tile& t, int3
   if (t.kind == 0) return SDD_OK;
   if (lds_shape_index(t) < 0) SDD_FAIL(SDD_EINVAL, "tile shape not in the built menu");
   const Range& R = p->ranges[r];
-  if (R.dec != 1) SDD_FAIL(SDD_EINVAL, "range %d: the LDS kernel takes 8-bit (undecimated) input", r);
+  const int es = R.dec == 1 ? 1 : 2;
+  const LdsShape& sh = kLdsShapes[lds_shape_index(t)];
+  if (lds_flush_period(sh, 255 * R.dec) < sh.cs)
+    SDD_FAIL(SDD_EINVAL, "range %d: decimation %d is too large for 16-bit accumulation", r,
+             R.dec);
   // the kernel takes a tile's first trial as its smallest delay
   for (size_t i = 1; i < R.dms.size(); ++i)
     if (R.dms[i] < R.dms[i - 1])
       SDD_FAIL(SDD_EINVAL, "range %d: the LDS kernel needs ascending trial DMs", r);
-  const LdsShape& sh = kLdsShapes[lds_shape_index(t)];
-  const int32_t dt = sh.d * sh.wd, tt = 512 * sh.m * sh.wt, nt = 64 * sh.wd * sh.wt;
+  const int32_t dt = sh.d * sh.wd, tt = lds_tile_samples(sh, es), nt = 64 * sh.wd * sh.wt;
   const int32_t span = range_span(p, r, dt);
-  const int64_t win = lds_window(tt, span);
+  const int64_t win = lds_window_bytes(tt, span, es);
   const int64_t lds = 4 * (int64_t)sh.cs * win;
   if (lds > 160 * 1024)
     SDD_FAIL(SDD_EINVAL, "range %d: delay span %d needs %lld bytes of LDS for this tile", r, span,

@@ -128,8 +128,11 @@ int32_t range_span(const sdd_plan* p, int32_t r, int32_t dm_tile);
 sdd_status check_tile_fits(const sdd_plan* p, int32_t r, const sdd_tile& t,
                            int32_t* span_out = nullptr);
 sdd_tile default_tile(const sdd_plan* p, int32_t r, int32_t* span_out);
-// LDS window bytes per copy for a tile of TT samples and the given span.
-inline int32_t lds_window(int32_t tt, int32_t span) { return (tt + span + 32 + 15) / 16 * 16; }
+// LDS window bytes per copy for a tile of tt samples of es bytes and the
+// given delay span (samples).
+inline int32_t lds_window_bytes(int32_t tt, int32_t span, int es) {
+  return (es * (tt + span + 32) + 15) / 16 * 16;
+}
 
 // ---- kernel launchers (k_*.hip) ----------------------------------------
 

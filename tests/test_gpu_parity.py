@@ -72,13 +72,26 @@ def test_multi_range_small_full_plane():
     d = oracle.delay_table(f, [37.0, 123.0], 2e-3)
     synth.inject_pulse(x, d[0], 1200, 6, 30.0)
     synth.inject_pulse(x, d[1], 3001, 24, 12.0)
+    orc = oracle.run(spec, x)
     for layout in ("chan", "time"):
         say(f"multi-range small, layout {layout}")
         plan = _make(kw, layout)
+        assert plan.get_tile(1)[0] >= 1  # decimated ranges take the LDS kernel too
         ph, res, g = gpu_run(plan, x, time_major=(layout == "time"))
-        orc = oracle.run(spec, x)
         compare_rows(spec, ph, orc)
         compare_search(spec, res, orc, full_rows=True)
+    # every tile shape, on all ranges (uint8 and uint16 inputs)
+    plan = _make(kw, "time")
+    n = 0
+    for tile in _menu_tiles():
+        try:
+            plan.set_tile(tile)
+        except Exception:
+            continue
+        ph, res, g = gpu_run(plan, x, time_major=True)
+        compare_rows(spec, ph, orc)
+        n += 1
+    assert n >= 3
 
 
 def test_full_band_bench_config_sampled_rows():
