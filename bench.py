@@ -160,6 +160,57 @@ def serve_bench(sdd, torch, nbeams: int, sat_chunks: int, rt_periods: int, max_b
     return out
 
 
+def batch_bench(sdd, torch, nbeams: int):
+    """nbeams beams of 4096 channels with owned lengths U[2^16, 2^18], 2048
+    trials 0-1000, widths 1..64: per-beam dedisperse_search calls vs one
+    batch call (persistent multi-beam launch) vs its graph replay. Inputs are
+    uniform random bytes made on the device (the integer path's timing does
+    not depend on the values)."""
+    import synth
+    params = synth.batched_beams(nbeams=nbeams)
+    f = np.linspace(750.0, 550.0, 4096)
+    plan = sdd.Plan(f, 81.92e-6, dm_list=np.linspace(0.0, 1000.0, 2048), widths=WIDTHS,
+                    cand_block=1024, threshold=7.0, layout="time")
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(4)
+    xs, outs = [], []
+    for n, _, _ in params:
+        xs.append(torch.randint(0, 256, (n + plan.overlap, 4096), dtype=torch.uint8,
+                                device="cuda:0", generator=gen))
+        outs.append(plan.alloc_search_out(4096))
+    units = sum(4096 * 2048 * n for n, _, _ in params)
+    side = torch.cuda.Stream()
+    res = {"beams": nbeams, "nchan": 4096, "ndm": 2048, "owned_total": int(sum(n for n, _, _ in params))}
+
+    def timed(fn, reps=2):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    wss = [plan.workspace(x.shape[0], with_planes=True) for x in xs[:1]]
+    ws_one = plan.workspace(max(x.shape[0] for x in xs), with_planes=True)
+
+    def per_beam():
+        for x, o in zip(xs, outs):
+            plan.dedisperse_search(x, out=o, workspace=ws_one, stream=side)
+    t = timed(per_beam)
+    res["per_beam_launches"] = {"seconds": round(t, 4), "value": round(units / t / 1e9, 2)}
+    del wss, ws_one
+    batch = sdd.Batch([(plan, x, None, o) for x, o in zip(xs, outs)])
+    ws = batch.workspace()
+    t = timed(lambda: batch.run(workspace=ws, stream=side))
+    res["persistent_batch"] = {"seconds": round(t, 4), "value": round(units / t / 1e9, 2)}
+    t = timed(lambda: batch.run(workspace=ws, graph=True, stream=side))
+    res["graph_replay"] = {"seconds": round(t, 4), "value": round(units / t / 1e9, 2)}
+    res["unit"] = UNIT
+    log(f"batch: {res}")
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -172,6 +223,8 @@ def main() -> int:
     ap.add_argument("--serve-chunks", type=int, default=4, help="chunks per beam, saturated run")
     ap.add_argument("--serve-periods", type=int, default=2, help="measured real-time periods")
     ap.add_argument("--serve-batch", type=int, default=16)
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-beams run")
+    ap.add_argument("--batch-beams", type=int, default=32)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: beams shard across GPUs with no exchange, so "
@@ -255,9 +308,13 @@ def main() -> int:
         log("timing the oracle on a bounded sample")
         res["cpu_baseline"] = cpu_baseline(w, plan.delays(0), args.cpu_rows)
     res["serving"] = None
-    if not args.no_serve:
-        del xt, planes, ws, out
+    res["batched"] = None
+    del xt, planes, ws, out
+    torch.cuda.empty_cache()
+    if not args.no_batch:
+        res["batched"] = batch_bench(sdd, torch, args.batch_beams)
         torch.cuda.empty_cache()
+    if not args.no_serve:
         res["serving"] = serve_bench(sdd, torch, args.serve_beams, args.serve_chunks,
                                      args.serve_periods, args.serve_batch, 2)
     print(json.dumps(res), flush=True)

@@ -148,9 +148,10 @@ typedef struct sdd_dm_stats {  /* moments of the owned samples of one trial */
 
 /* Tile shape of the dedispersion kernel (a fixed menu; see sdd_tile_menu).
  * kind 0: direct kernel (one thread per DM and 4 samples, no LDS);
- * kind 1..4: LDS-tiled kernel, 1 + variant flags (1: LDS stages prefetched
- * two ahead, 2: two 64-bit LDS reads per 8 samples instead of 64 + 32 bits).
- * The other fields apply to the LDS kernel. */
+ * kind 1..8: LDS-tiled kernel, 1 + variant flags (1: LDS stages prefetched
+ * two ahead; 2: two 64-bit LDS reads per 8 samples instead of 64 + 32 bits;
+ * 4: the next stage's window bases come from delays fetched a stage
+ * earlier). The other fields apply to the LDS kernel. */
 typedef struct sdd_tile {
   int32_t kind;
   int32_t dm_per_wave;     /* DM trials per wavefront */

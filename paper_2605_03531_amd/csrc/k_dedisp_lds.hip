@@ -87,6 +87,17 @@ __device__ __forceinline__ void dd_tile(const LdsArgs a, int32_t dtile, int32_t 
   // ---- staging: global -> registers -> two LDS copies ----
   constexpr bool PREF2 = (F & 1) != 0;  // prefetch LDS stages two ahead
   constexpr bool WIDE = (F & 2) != 0;   // 2 x 64-bit reads instead of 64 + 32
+  // window bases from delays fetched a stage earlier (no dependent global
+  // load in the staging path); element and delay lane maps computed once
+  constexpr bool EARLY = (F & 4) != 0;
+  static_assert(!(EARLY && PREF2), "one prefetch scheme at a time");
+  int32_t ecs[NLD], eq[NLD];
+#pragma unroll
+  for (int k = 0; k < NLD; ++k) {
+    const int32_t e = tid + k * NT;
+    ecs[k] = e / wq;
+    eq[k] = e - ecs[k] * wq;
+  }
   uint4 st[NLD];
   uint4 st2[PREF2 ? NLD : 1];
   auto load_stage = [&](int32_t cbase, uint4 (&dst)[NLD]) {
@@ -114,13 +125,42 @@ __device__ __forceinline__ void dd_tile(const LdsArgs a, int32_t dtile, int32_t 
       dst[k] = v;
     }
   };
+  // staging with the window bases taken from a delay vector of the stage
+  // (entry cs*(D+1) holds d(c, i0) of slot cs)
+  auto load_stage_bases = [&](int32_t cbase, uint4 (&dst)[NLD], const int32_t* dv) {
+#pragma unroll
+    for (int k = 0; k < NLD; ++k) {
+      const int32_t cs = ecs[k], q = eq[k];
+      const int32_t c = cbase + cs;
+      const int32_t idx = (cs < CS ? cs : 0) * (D + 1);
+      int32_t b0 = __shfl(dv[0], idx & 63, 64);
+      if ((CS * (D + 1) + 63) / 64 > 1) {
+        const int32_t b1 = __shfl(dv[((CS * (D + 1) + 63) / 64) - 1], idx & 63, 64);
+        b0 = idx < 64 ? b0 : b1;
+      }
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (cs < CS && c < nchan) {
+        const int64_t g = ES * (t0 + (int64_t)(b0 & ~15)) + 16 * q;
+        const int64_t row_bytes = ES * a.x_len;
+        const uint8_t* src = a.x + (int64_t)c * a.x_pitch * ES + g;
+        if (a.aligned && g + 16 <= row_bytes) {
+          v = *reinterpret_cast<const uint4*>(src);
+        } else {
+          uint32_t w[4] = {0u, 0u, 0u, 0u};
+          for (int bb = 0; bb < 16; ++bb)
+            if (g + bb < row_bytes) w[bb >> 2] |= (uint32_t)src[bb] << (8 * (bb & 3));
+          v = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+      }
+      dst[k] = v;
+    }
+  };
   auto store_stage = [&](int32_t which, const uint4 (&src)[NLD]) {
     uint8_t* base = lds + which * buf;
 #pragma unroll
     for (int k = 0; k < NLD; ++k) {
-      const int32_t e = tid + k * NT;
-      const int32_t cs = e / wq;
-      const int32_t q = e - cs * wq;
+      const int32_t cs = ecs[k];
+      const int32_t q = eq[k];
       if (cs < CS) {
         uint8_t* c0 = base + cs * slot + 16 * q;  // copy 0
         uint8_t* c1 = c0 + win;                   // copy 1: byte j holds window byte j + 4
@@ -152,15 +192,20 @@ __device__ __forceinline__ void dd_tile(const LdsArgs a, int32_t dtile, int32_t 
   // A channel past nchan gets delay 0 and an all-zero window.
   constexpr int DE = D + 1;
   constexpr int NDV = (CS * DE + 63) / 64;  // VGPRs holding one stage's delays
+  int32_t dl_cs[NDV], dl_i[NDV];
+#pragma unroll
+  for (int v = 0; v < NDV; ++v) {
+    const int32_t k = 64 * v + lane;
+    const int32_t cs = k / DE, e = k - cs * DE;
+    int32_t i = e == 0 ? i0 : i0 + wd * D + e - 1;
+    dl_cs[v] = k < CS * DE ? cs : CS;
+    dl_i[v] = i < ndm ? i : ndm - 1;
+  }
   auto load_delays = [&](int32_t cbase, int32_t (&out)[NDV]) {
 #pragma unroll
     for (int v = 0; v < NDV; ++v) {
-      const int32_t k = 64 * v + lane;
-      const int32_t cs = k / DE, e = k - cs * DE;
-      const int32_t c = cbase + cs;
-      int32_t i = e == 0 ? i0 : i0 + wd * D + e - 1;
-      i = i < ndm ? i : ndm - 1;
-      out[v] = (k < CS * DE && c < nchan) ? dcm[(int64_t)c * ndm + i] : 0;
+      const int32_t c = cbase + dl_cs[v];
+      out[v] = (dl_cs[v] < CS && c < nchan) ? dcm[(int64_t)c * ndm + dl_i[v]] : 0;
     }
   };
   // entry k of the current stage, as a wave-uniform scalar
@@ -170,9 +215,15 @@ __device__ __forceinline__ void dd_tile(const LdsArgs a, int32_t dtile, int32_t 
   const int32_t lane_off = 8 * lane + ES * TW * wt;  // bytes
   const int32_t flush_every = ES == 1 ? 256 : a.flush;
   int32_t dnext[NDV];
-  int32_t dnext2[PREF2 ? NDV : 1];
-  load_stage(0, st);
-  load_delays(0, dnext);
+  int32_t dnext2[(PREF2 || EARLY) ? NDV : 1];
+  if constexpr (EARLY) {
+    load_delays(0, dnext);
+    load_stage_bases(0, st, dnext);
+    if (nstages > 1) load_delays(CS, dnext2);
+  } else {
+    load_stage(0, st);
+    load_delays(0, dnext);
+  }
   store_stage(0, st);
   if constexpr (PREF2) {
     if (nstages > 1) {
@@ -186,7 +237,14 @@ __device__ __forceinline__ void dd_tile(const LdsArgs a, int32_t dtile, int32_t 
     int32_t dcur[NDV];
 #pragma unroll
     for (int v = 0; v < NDV; ++v) dcur[v] = dnext[v];
-    if constexpr (PREF2) {
+    if constexpr (EARLY) {
+      // stage s+1's delays arrived a stage ago: stage its data now, fetch
+      // the delays of stage s+2
+      if (s + 1 < nstages) load_stage_bases(cbase + CS, st, dnext2);
+#pragma unroll
+      for (int v = 0; v < NDV; ++v) dnext[v] = dnext2[v];
+      if (s + 2 < nstages) load_delays(cbase + 2 * CS, dnext2);
+    } else if constexpr (PREF2) {
       // stage s+1 is in st (loaded one stage ago); fetch stage s+2
       if (s + 2 < nstages) {
         load_stage(cbase + 2 * CS, st2);
@@ -383,6 +441,10 @@ hipError_t launch_one(const LdsArgs& a, hipStream_t s) {
 // The built menu, {D, M, WD, WT, CS, NLD, F}; sdd_tile carries it as
 // {kind 1 + F, D, WD, WT, pairs per lane = 4*M, CS}.
 #define SDD_LDS_SHAPES(X)      \
+  X(4, 1, 8, 2, 4, 1, 4)       \
+  X(4, 1, 8, 2, 4, 1, 6)       \
+  X(4, 1, 16, 1, 4, 1, 4)      \
+  X(8, 1, 8, 1, 4, 2, 4)       \
   X(4, 1, 8, 2, 4, 1, 0)       \
   X(4, 1, 8, 2, 4, 1, 1)       \
   X(4, 1, 8, 2, 4, 1, 2)       \

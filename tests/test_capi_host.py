@@ -168,8 +168,9 @@ def test_single_hip_runtime_in_process():
 def test_unsorted_dm_list_uses_the_direct_kernel():
     p = sdd.Plan([500.0, 400.0, 300.0], 1e-3, dm_list=[5.0, 0.0, 3.0])
     assert p.get_tile(0)[0] == 0
-    lds_tiles = [t for t in sdd.tile_menu() if t[0] == 1]
-    with pytest.raises(sdd.SddError):
-        p.set_tile(lds_tiles[0])
+    lds_tiles = [t for t in sdd.tile_menu() if t[0] >= 1]
+    for t in lds_tiles:
+        with pytest.raises(sdd.SddError):
+            p.set_tile(t)
     q = sdd.Plan([500.0, 400.0, 300.0], 1e-3, dm_list=[0.0, 3.0, 5.0])
-    assert q.get_tile(0)[0] == 1
+    assert q.get_tile(0)[0] >= 1
