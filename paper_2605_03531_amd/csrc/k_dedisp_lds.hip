@@ -24,19 +24,8 @@
 namespace sdd {
 namespace {
 
-__device__ __forceinline__ uint32_t sel_pair(uint32_t s) {
-  // bytes s, s+1 of an 8-byte (hi:lo) pair into the low bytes of two 16-bit
-  // fields; selector byte 0x0c yields zero
-  return s | 0x00000c00u | ((s + 1u) << 16) | 0x0c000000u;
-}
-
 // One DT x TT tile of one job. Every thread of the workgroup calls it; it
 // returns after a barrier, so the caller may reuse the LDS at once.
-__device__ __forceinline__ uint32_t sel_quad(uint32_t s) {
-  // bytes s..s+3 of an 8-byte (hi:lo) pair, in order
-  return s | ((s + 1u) << 8) | ((s + 2u) << 16) | ((s + 3u) << 24);
-}
-
 // ES = input element bytes: 1 (uint8 rows) or 2 (uint16 rows of a decimated
 // range). A lane always owns 8 bytes of a 512-byte chunk: 8 uint8 samples
 // (four 16-bit pairs after widening) or 4 uint16 samples (two pairs as read).
@@ -91,6 +80,8 @@ __device__ __forceinline__ void dd_tile(const LdsArgs a, int32_t dtile, int32_t 
   // load in the staging path); element and delay lane maps computed once
   constexpr bool EARLY = (F & 4) != 0;
   static_assert(!(EARLY && PREF2), "one prefetch scheme at a time");
+  // the staging must hold a stage's windows at zero delay span at least
+  static_assert(CS * (ES * TT + 32 * ES) <= 16 * NLD * NT, "staging too small for the tile");
   int32_t ecs[NLD], eq[NLD];
 #pragma unroll
   for (int k = 0; k < NLD; ++k) {
@@ -193,6 +184,7 @@ __device__ __forceinline__ void dd_tile(const LdsArgs a, int32_t dtile, int32_t 
   constexpr int DE = D + 1;
   constexpr int NDV = (CS * DE + 63) / 64;  // VGPRs holding one stage's delays
   int32_t dl_cs[NDV], dl_i[NDV];
+  bool dl_e0[NDV];
 #pragma unroll
   for (int v = 0; v < NDV; ++v) {
     const int32_t k = 64 * v + lane;
@@ -200,12 +192,25 @@ __device__ __forceinline__ void dd_tile(const LdsArgs a, int32_t dtile, int32_t 
     int32_t i = e == 0 ? i0 : i0 + wd * D + e - 1;
     dl_cs[v] = k < CS * DE ? cs : CS;
     dl_i[v] = i < ndm ? i : ndm - 1;
+    dl_e0[v] = e == 0;
   }
+  // Entry 0 of a slot keeps the raw delay d(c, i0) (the window base); entry
+  // 1+d holds the packed read position of trial d: bits 0-19 the LDS byte
+  // offset of its 8-byte word inside the slot (copy 1 when the offset within
+  // the word is >= 4), bits 20-21 the remaining byte shift. Computing it here,
+  // once per stage for all entries across the lanes, keeps the per-trial work
+  // in the loop to one v_readlane and a few scalar operations.
   auto load_delays = [&](int32_t cbase, int32_t (&out)[NDV]) {
 #pragma unroll
     for (int v = 0; v < NDV; ++v) {
       const int32_t c = cbase + dl_cs[v];
-      out[v] = (dl_cs[v] < CS && c < nchan) ? dcm[(int64_t)c * ndm + dl_i[v]] : 0;
+      const bool ok = dl_cs[v] < CS && c < nchan;
+      const int32_t* row = dcm + (int64_t)(ok ? c : 0) * ndm;
+      const int32_t dv = ok ? row[dl_i[v]] : 0;
+      const int32_t d0 = ok ? row[i0] : 0;
+      const int32_t o = ES * (dv - (d0 & ~15));
+      const int32_t ad = (o & ~7) + ((o & 4) ? win : 0);
+      out[v] = dl_e0[v] ? d0 : (ad | ((o & 3) << 20));
     }
   };
   // entry k of the current stage, as a wave-uniform scalar
@@ -266,22 +271,21 @@ __device__ __forceinline__ void dd_tile(const LdsArgs a, int32_t dtile, int32_t 
     const uint8_t* bufp = lds + (s & 1) * buf + lane_off;
 #pragma unroll
     for (int cc = 0; cc < CS; cc += 2) {
-      const int32_t baseA = SDD_DELAY(cc * DE) & ~15;
-      const int32_t baseB = SDD_DELAY((cc + 1) * DE) & ~15;
       const uint8_t* slotA = bufp + cc * slot;
       const uint8_t* slotB = slotA + slot;
 #pragma unroll
       for (int d = 0; d < D; ++d) {
-        // byte offsets into the windows
-        const int32_t oA = ES * (SDD_DELAY(cc * DE + 1 + d) - baseA);
-        const int32_t oB = ES * (SDD_DELAY((cc + 1) * DE + 1 + d) - baseB);
-        // copy 1 when the byte offset within the 8-byte word is >= 4
-        const int32_t adA = (oA & ~7) + ((oA & 4) ? win : 0);
-        const int32_t adB = (oB & ~7) + ((oB & 4) ? win : 0);
-        const uint32_t sA0 = ES == 1 ? sel_pair(oA & 3) : sel_quad(oA & 3);
-        const uint32_t sA2 = sel_pair((oA & 3) + 2);
-        const uint32_t sB0 = ES == 1 ? sel_pair(oB & 3) : sel_quad(oB & 3);
-        const uint32_t sB2 = sel_pair((oB & 3) + 2);
+        const uint32_t wA = (uint32_t)SDD_DELAY(cc * DE + 1 + d);
+        const uint32_t wB = (uint32_t)SDD_DELAY((cc + 1) * DE + 1 + d);
+        const int32_t adA = (int32_t)(wA & 0xfffffu);
+        const int32_t adB = (int32_t)(wB & 0xfffffu);
+        const uint32_t rA = wA >> 20, rB = wB >> 20;
+        // v_perm selectors: bytes r, r+1 (and r+2, r+3) into 16-bit fields for
+        // uint8 input; bytes r..r+3 in order for uint16 input
+        const uint32_t sA0 = ES == 1 ? 0x0c010c00u + rA * 0x00010001u : 0x03020100u + rA * 0x01010101u;
+        const uint32_t sB0 = ES == 1 ? 0x0c010c00u + rB * 0x00010001u : 0x03020100u + rB * 0x01010101u;
+        const uint32_t sA2 = sA0 + 0x00020002u;
+        const uint32_t sB2 = sB0 + 0x00020002u;
 #pragma unroll
         for (int m = 0; m < M; ++m) {
           const uint8_t* pA = slotA + adA + 512 * m;
@@ -441,17 +445,20 @@ hipError_t launch_one(const LdsArgs& a, hipStream_t s) {
 // The built menu, {D, M, WD, WT, CS, NLD, F}; sdd_tile carries it as
 // {kind 1 + F, D, WD, WT, pairs per lane = 4*M, CS}.
 #define SDD_LDS_SHAPES(X)      \
-  X(4, 1, 8, 2, 4, 1, 4)       \
-  X(4, 1, 8, 2, 4, 1, 6)       \
+  X(2, 2, 4, 1, 4, 2, 4)       \
+  X(2, 1, 4, 1, 4, 1, 4)       \
+  X(4, 1, 4, 1, 4, 2, 4)       \
+  X(4, 1, 2, 2, 4, 2, 4)       \
+  X(2, 2, 2, 1, 4, 3, 4)       \
+  X(4, 1, 2, 1, 4, 2, 4)       \
+  X(4, 1, 8, 1, 4, 1, 4)       \
+  X(4, 1, 4, 2, 4, 2, 4)       \
+  X(2, 1, 8, 1, 4, 1, 4)       \
   X(4, 1, 16, 1, 4, 1, 4)      \
-  X(8, 1, 8, 1, 4, 2, 4)       \
+  X(4, 1, 8, 2, 4, 1, 4)       \
   X(4, 1, 8, 2, 4, 1, 0)       \
   X(4, 1, 8, 2, 4, 1, 1)       \
-  X(4, 1, 8, 2, 4, 1, 2)       \
-  X(4, 1, 8, 2, 4, 1, 3)       \
-  X(4, 1, 16, 1, 4, 1, 0)      \
-  X(4, 1, 16, 1, 4, 1, 3)      \
-  X(8, 1, 8, 1, 4, 2, 0)       \
+  X(4, 1, 8, 2, 4, 1, 6)       \
   X(8, 1, 4, 1, 8, 4, 0)
 
 #define SDD_SHAPE_ROW(d, m, wd, wt, cs, nld, f) {d, m, wd, wt, cs, nld, f},

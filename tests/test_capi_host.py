@@ -148,7 +148,8 @@ def test_compute_calls_validate_before_touching_the_device():
 def test_tile_menu_and_set_tile():
     menu = sdd.tile_menu()
     assert (0, 0, 0, 0, 0, 0) in menu
-    p = sdd.Plan([500.0, 300.0], 1e-3, dm_list=[0.0, 5.0])
+    # a delay span of 15 samples fits every shape's staging
+    p = sdd.Plan([500.0, 300.0], 1e-3, dm_list=[0.0, 0.5])
     for t in menu:
         p.set_tile(t)
         assert p.get_tile(0) == t
