@@ -147,6 +147,7 @@ extern "C" sdd_status sdd_autotune(sdd_plan* p, int64_t nsamp_in, const char* ca
       a.max_val = 255;
       a.tile = t;
       a.span = span;
+      a.max_delay = R.max_delay;
       if (launch_dedisperse(a, s) != hipSuccess) continue;  // warm-up
       (void)hipEventRecord(e0, s);
       const int reps = 2;

@@ -91,6 +91,7 @@ sdd_status prep_item(const sdd_plan* p, const CallGeom& cg, const uint8_t* d_in,
     a.max_val = 255 * R.dec;
     a.tile = R.tile;
     a.span = R.tile_span;
+    a.max_delay = R.max_delay;
     if (a.cols + R.max_delay > a.x_len)
       SDD_FAIL(SDD_EINVAL, "internal: range %zu input too short", r);
     jobs->push_back(a);

@@ -1,6 +1,8 @@
 // Brute-force incoherent dedispersion kernels (Section 3.2: every trial DM
 // sums all channels along its delay curve; Section 2.1: many trial DMs).
 //   plane[i][j] = sum_c x[c][j + delay[c][i]],  j < cols   (exact uint32)
+#include <algorithm>
+
 #include "k_dedisp_lds.h"
 #include "sdd_internal.h"
 
@@ -74,6 +76,15 @@ int lds_args_for(const DedispArgs& a, LdsArgs* out) {
   l.aligned = ((uintptr_t)a.x % 16 == 0) && ((a.x_pitch * es) % 16 == 0);
   l.es = es;
   l.flush = flush;
+  // the kernel forms row offsets of one stage in 32 bits
+  const int64_t stage_bytes = (int64_t)sh.cs * a.x_pitch * es + l.win + 32 + (int64_t)es * a.max_delay;
+  if (stage_bytes >= ((int64_t)1 << 32)) return -1;
+  // tile t is interior when its last staging byte, es*(t*tt + max_delay) +
+  // win + 4, is inside the row
+  const int64_t room = (int64_t)es * (a.x_len - a.max_delay) - l.win - 4;
+  int64_t n_int = 0;
+  if (l.aligned && room >= 0) n_int = room / ((int64_t)es * tt) + 1;
+  l.n_tt_interior = (int32_t)std::min<int64_t>(n_int, l.n_ttiles);
   return shape;
 }
 

@@ -20,6 +20,7 @@ struct LdsArgs {
   int32_t aligned;        // rows start 16-byte aligned
   int32_t es;             // element bytes: 1 or 2
   int32_t flush;          // channels per 16-bit flush (es == 2; multiple of the stage)
+  int32_t n_tt_interior;  // time tiles [0, n) whose staging loads all lie inside the rows
 };
 
 
@@ -31,7 +32,7 @@ struct LdsShape {
   int wt;     // wavefronts along time
   int cs;     // channels per LDS stage
   int nld;    // 16-byte staging loads per thread per stage
-  int f;      // variant flags: 1 = stages prefetched two ahead, 2 = 2 x 64-bit reads
+  int f;      // variant flags: 2 = third word through a 64-bit read
 };
 
 // Samples one tile of a shape covers for elements of es bytes.

@@ -29,9 +29,11 @@ namespace {
 // ES = input element bytes: 1 (uint8 rows) or 2 (uint16 rows of a decimated
 // range). A lane always owns 8 bytes of a 512-byte chunk: 8 uint8 samples
 // (four 16-bit pairs after widening) or 4 uint16 samples (two pairs as read).
-template <int D, int M, int WD, int WT, int CS, int NLD, int F, int ES>
-__device__ __forceinline__ void dd_tile(const LdsArgs a, int32_t dtile, int32_t ttile,
-                                        uint8_t* __restrict__ lds) {
+// INTERIOR: every staging load of the tile lies inside the rows and the rows
+// are 16-byte aligned, so the loads need no per-element checks.
+template <int D, int M, int WD, int WT, int CS, int NLD, int F, int ES, bool INTERIOR>
+__device__ __forceinline__ void dd_tile_impl(const LdsArgs& a, int32_t dtile, int32_t ttile,
+                                             uint8_t* __restrict__ lds) {
   constexpr int NT = 64 * WD * WT;
   constexpr int DT = D * WD;
   constexpr int SPL = 8 / ES;       // samples per lane per chunk
@@ -39,6 +41,11 @@ __device__ __forceinline__ void dd_tile(const LdsArgs a, int32_t dtile, int32_t 
   constexpr int NPK = SPL / 2;      // packed 16-bit pairs per lane per chunk
   constexpr int TW = CH * M;        // samples per time group of waves
   constexpr int TT = TW * WT;
+  constexpr bool WIDE = (F & 2) != 0;  // third word through a 64-bit read
+  constexpr int NDV = (CS * D + 63) / 64;  // VGPRs holding one stage's read positions
+  static_assert(CS % 2 == 0, "channels are added in pairs");
+  // the staging must hold a stage's windows at zero delay span at least
+  static_assert(CS * (ES * TT + 32 * ES) <= 16 * NLD * NT, "staging too small for the tile");
   const int32_t i0 = dtile * DT;
   const int64_t t0 = (int64_t)ttile * TT;
 
@@ -47,19 +54,12 @@ __device__ __forceinline__ void dd_tile(const LdsArgs a, int32_t dtile, int32_t 
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wd = wave % WD, wt = wave / WD;
   const int32_t ndm = a.ndm, nchan = a.nchan;
-  const int32_t* __restrict__ dcm = a.delays;
-
-  int32_t iw[D];
-#pragma unroll
-  for (int d = 0; d < D; ++d) {
-    const int32_t i = i0 + wd * D + d;
-    iw[d] = i < ndm ? i : ndm - 1;
-  }
-
   const int32_t win = a.win;            // bytes per copy, multiple of 16
   const int32_t slot = 2 * win;         // copy 0 + copy 1
   const int32_t buf = CS * slot;
   const int32_t wq = win >> 4;          // 16-byte elements per window
+  const int64_t pitch_bytes = (int64_t)ES * a.x_pitch;
+  const int64_t row_bytes = (int64_t)ES * a.x_len;
 
   uint32_t acc[D][M][NPK];
   uint32_t wide[D][M][SPL];
@@ -74,91 +74,83 @@ __device__ __forceinline__ void dd_tile(const LdsArgs a, int32_t dtile, int32_t 
     }
 
   // ---- staging: global -> registers -> two LDS copies ----
-  constexpr bool PREF2 = (F & 1) != 0;  // prefetch LDS stages two ahead
-  constexpr bool WIDE = (F & 2) != 0;   // 2 x 64-bit reads instead of 64 + 32
-  // window bases from delays fetched a stage earlier (no dependent global
-  // load in the staging path); element and delay lane maps computed once
-  constexpr bool EARLY = (F & 4) != 0;
-  static_assert(!(EARLY && PREF2), "one prefetch scheme at a time");
-  // the staging must hold a stage's windows at zero delay span at least
-  static_assert(CS * (ES * TT + 32 * ES) <= 16 * NLD * NT, "staging too small for the tile");
-  int32_t ecs[NLD], eq[NLD];
+  // Thread element k covers 16 bytes (q) of the window of slot ecs[k]. Its
+  // loads address (uniform stage base) + (32-bit per-lane offset); the
+  // window starts at sample t0 + (d(c, i0) & ~15), with d(c, i0) loaded two
+  // stages ahead by the element itself.
+  int32_t ecs[NLD];
+  uint32_t eoff[NLD];   // cs * pitch + 16 q (bytes from the stage's row base)
+  int32_t eq16[NLD];    // 16 q
+  uint32_t ebase[NLD];  // cs * ndm (delay-table entries from the stage's first row)
+  int32_t elds[NLD];    // cs * slot + 16 q
 #pragma unroll
   for (int k = 0; k < NLD; ++k) {
     const int32_t e = tid + k * NT;
-    ecs[k] = e / wq;
-    eq[k] = e - ecs[k] * wq;
+    const int32_t cs = e / wq;
+    const int32_t q = e - cs * wq;
+    ecs[k] = cs < CS ? cs : CS;
+    const int32_t csv = cs < CS ? cs : 0;
+    eoff[k] = (uint32_t)(csv * pitch_bytes) + 16u * (uint32_t)q;
+    eq16[k] = 16 * q;
+    ebase[k] = (uint32_t)(csv * ndm);
+    elds[k] = csv * slot + 16 * q;
   }
+  const uint8_t* __restrict__ xs = a.x + ES * t0;  // stage 0 row base (uniform)
+  const int32_t* __restrict__ ds = a.delays;       // stage 0 delay row base (uniform)
+
   uint4 st[NLD];
-  uint4 st2[PREF2 ? NLD : 1];
-  auto load_stage = [&](int32_t cbase, uint4 (&dst)[NLD]) {
+  uint32_t ext[NLD];
+  // d(c, i0) of each element's channel at a stage (0 past the last channel)
+  auto load_bases = [&](int32_t s, int32_t (&dst)[NLD]) {
+    const int32_t* row = ds + (int64_t)s * CS * ndm + i0;
 #pragma unroll
     for (int k = 0; k < NLD; ++k) {
-      const int32_t e = tid + k * NT;
-      const int32_t cs = e / wq;
-      const int32_t q = e - cs * wq;
-      const int32_t c = cbase + cs;
-      uint4 v = make_uint4(0u, 0u, 0u, 0u);
-      if (cs < CS && c < nchan) {
-        // byte g of channel c's row; the window starts at sample t0 + d(c,i0) & ~15
-        const int64_t g = ES * (t0 + (int64_t)(dcm[(int64_t)c * ndm + i0] & ~15)) + 16 * q;
-        const int64_t row_bytes = ES * a.x_len;
-        const uint8_t* src = a.x + (int64_t)c * a.x_pitch * ES + g;
-        if (a.aligned && g + 16 <= row_bytes) {
-          v = *reinterpret_cast<const uint4*>(src);
-        } else {
-          uint32_t w[4] = {0u, 0u, 0u, 0u};
-          for (int bb = 0; bb < 16; ++bb)
-            if (g + bb < row_bytes) w[bb >> 2] |= (uint32_t)src[bb] << (8 * (bb & 3));
-          v = make_uint4(w[0], w[1], w[2], w[3]);
-        }
-      }
-      dst[k] = v;
+      const bool ok = ecs[k] < CS && s * CS + ecs[k] < nchan;
+      dst[k] = ok ? row[ebase[k]] : 0;
     }
   };
-  // staging with the window bases taken from a delay vector of the stage
-  // (entry cs*(D+1) holds d(c, i0) of slot cs)
-  auto load_stage_bases = [&](int32_t cbase, uint4 (&dst)[NLD], const int32_t* dv) {
+  auto load_data = [&](int32_t s, const int32_t (&bases)[NLD]) {
+    const uint8_t* row = xs + (int64_t)s * CS * pitch_bytes;
 #pragma unroll
     for (int k = 0; k < NLD; ++k) {
-      const int32_t cs = ecs[k], q = eq[k];
-      const int32_t c = cbase + cs;
-      const int32_t idx = (cs < CS ? cs : 0) * (D + 1);
-      int32_t b0 = __shfl(dv[0], idx & 63, 64);
-      if ((CS * (D + 1) + 63) / 64 > 1) {
-        const int32_t b1 = __shfl(dv[((CS * (D + 1) + 63) / 64) - 1], idx & 63, 64);
-        b0 = idx < 64 ? b0 : b1;
-      }
+      const bool ok = ecs[k] < CS && s * CS + ecs[k] < nchan;
+      const uint32_t off = eoff[k] + (uint32_t)(ES * (bases[k] & ~15));
       uint4 v = make_uint4(0u, 0u, 0u, 0u);
-      if (cs < CS && c < nchan) {
-        const int64_t g = ES * (t0 + (int64_t)(b0 & ~15)) + 16 * q;
-        const int64_t row_bytes = ES * a.x_len;
-        const uint8_t* src = a.x + (int64_t)c * a.x_pitch * ES + g;
-        if (a.aligned && g + 16 <= row_bytes) {
+      uint32_t x4 = 0u;
+      if (ok) {
+        const uint8_t* src = row + off;
+        if constexpr (INTERIOR) {
           v = *reinterpret_cast<const uint4*>(src);
+          x4 = *reinterpret_cast<const uint32_t*>(src + 16);
         } else {
-          uint32_t w[4] = {0u, 0u, 0u, 0u};
-          for (int bb = 0; bb < 16; ++bb)
-            if (g + bb < row_bytes) w[bb >> 2] |= (uint32_t)src[bb] << (8 * (bb & 3));
+          // byte g of the row; zero past its end
+          const int64_t g = ES * (t0 + (bases[k] & ~15)) + eq16[k];
+          uint32_t w[5] = {0u, 0u, 0u, 0u, 0u};
+          if (a.aligned && g + 20 <= row_bytes) {
+            const uint4 t = *reinterpret_cast<const uint4*>(src);
+            w[0] = t.x; w[1] = t.y; w[2] = t.z; w[3] = t.w;
+            w[4] = *reinterpret_cast<const uint32_t*>(src + 16);
+          } else {
+            for (int bb = 0; bb < 20; ++bb)
+              if (g + bb < row_bytes) w[bb >> 2] |= (uint32_t)src[bb] << (8 * (bb & 3));
+          }
           v = make_uint4(w[0], w[1], w[2], w[3]);
+          x4 = w[4];
         }
       }
-      dst[k] = v;
+      st[k] = v;
+      ext[k] = x4;
     }
   };
-  auto store_stage = [&](int32_t which, const uint4 (&src)[NLD]) {
+  auto store_stage = [&](int32_t which) {
     uint8_t* base = lds + which * buf;
 #pragma unroll
     for (int k = 0; k < NLD; ++k) {
-      const int32_t cs = ecs[k];
-      const int32_t q = eq[k];
-      if (cs < CS) {
-        uint8_t* c0 = base + cs * slot + 16 * q;  // copy 0
-        uint8_t* c1 = c0 + win;                   // copy 1: byte j holds window byte j + 4
-        *reinterpret_cast<uint4*>(c0) = src[k];
-        if (q > 0) *reinterpret_cast<uint32_t*>(c1 - 4) = src[k].x;
-        *reinterpret_cast<uint2*>(c1) = make_uint2(src[k].y, src[k].z);
-        *reinterpret_cast<uint32_t*>(c1 + 8) = src[k].w;
+      if (ecs[k] < CS) {
+        uint8_t* c0 = base + elds[k];
+        // copy 0 as loaded; copy 1 byte j = window byte j + 4
+        *reinterpret_cast<uint4*>(c0) = st[k];
+        *reinterpret_cast<uint4*>(c0 + win) = make_uint4(st[k].y, st[k].z, st[k].w, ext[k]);
       }
     }
   };
@@ -176,97 +168,74 @@ __device__ __forceinline__ void dd_tile(const LdsArgs a, int32_t dtile, int32_t 
         }
   };
 
-  // Delays of the next stage travel with its data: lane k < CS*(D+1) loads
-  // one entry (slot k/(D+1); entry 0 = the tile's first trial, entry 1+d =
-  // this wavefront's trial d) through the vector memory path, so the compute
-  // loop holds no scalar-memory waits that would also drain its LDS reads.
-  // A channel past nchan gets delay 0 and an all-zero window.
-  constexpr int DE = D + 1;
-  constexpr int NDV = (CS * DE + 63) / 64;  // VGPRs holding one stage's delays
-  int32_t dl_cs[NDV], dl_i[NDV];
-  bool dl_e0[NDV];
+  // Read positions of a stage: lane k < CS*D holds entry k = slot*D + d,
+  // trial d of this wavefront in that slot's channel, packed as bits 0-19 the
+  // LDS byte offset of its 8-byte word inside the slot (copy 1 when the
+  // offset within the word is >= 4) and bits 20-21 the remaining byte shift.
+  // They are computed here across the lanes, once per stage, so the compute
+  // loop needs one v_readlane and a few scalar operations per channel and
+  // trial, and no scalar-memory waits that would also drain its LDS reads.
+  // A channel past nchan gets offset 0 into its all-zero window.
+  int32_t dl_cs[NDV];
+  uint32_t dl_off[NDV], dl_off0[NDV];
 #pragma unroll
   for (int v = 0; v < NDV; ++v) {
     const int32_t k = 64 * v + lane;
-    const int32_t cs = k / DE, e = k - cs * DE;
-    int32_t i = e == 0 ? i0 : i0 + wd * D + e - 1;
-    dl_cs[v] = k < CS * DE ? cs : CS;
-    dl_i[v] = i < ndm ? i : ndm - 1;
-    dl_e0[v] = e == 0;
+    const int32_t cs = k / D, d = k - cs * D;
+    const int32_t i = i0 + wd * D + d;
+    dl_cs[v] = k < CS * D ? cs : CS;
+    const int32_t csv = k < CS * D ? cs : 0;
+    dl_off[v] = (uint32_t)(csv * ndm + (i < ndm ? i : ndm - 1));
+    dl_off0[v] = (uint32_t)(csv * ndm + i0);
   }
-  // Entry 0 of a slot keeps the raw delay d(c, i0) (the window base); entry
-  // 1+d holds the packed read position of trial d: bits 0-19 the LDS byte
-  // offset of its 8-byte word inside the slot (copy 1 when the offset within
-  // the word is >= 4), bits 20-21 the remaining byte shift. Computing it here,
-  // once per stage for all entries across the lanes, keeps the per-trial work
-  // in the loop to one v_readlane and a few scalar operations.
-  auto load_delays = [&](int32_t cbase, int32_t (&out)[NDV]) {
+  int32_t rdv[NDV], rd0[NDV];
+  auto load_words = [&](int32_t s) {
+    const int32_t* row = ds + (int64_t)s * CS * ndm;
 #pragma unroll
     for (int v = 0; v < NDV; ++v) {
-      const int32_t c = cbase + dl_cs[v];
-      const bool ok = dl_cs[v] < CS && c < nchan;
-      const int32_t* row = dcm + (int64_t)(ok ? c : 0) * ndm;
-      const int32_t dv = ok ? row[dl_i[v]] : 0;
-      const int32_t d0 = ok ? row[i0] : 0;
-      const int32_t o = ES * (dv - (d0 & ~15));
-      const int32_t ad = (o & ~7) + ((o & 4) ? win : 0);
-      out[v] = dl_e0[v] ? d0 : (ad | ((o & 3) << 20));
+      const bool ok = dl_cs[v] < CS && s * CS + dl_cs[v] < nchan;
+      rdv[v] = ok ? row[dl_off[v]] : 0;
+      rd0[v] = ok ? row[dl_off0[v]] : 0;
     }
   };
+  auto pack_words = [&](int32_t (&out)[NDV]) {
+#pragma unroll
+    for (int v = 0; v < NDV; ++v) {
+      const int32_t o = ES * (rdv[v] - (rd0[v] & ~15));
+      const int32_t ad = (o & ~7) + ((o & 4) ? win : 0);
+      out[v] = ad | ((o & 3) << 20);
+    }
+  };
+
   // entry k of the current stage, as a wave-uniform scalar
-#define SDD_DELAY(k) __builtin_amdgcn_readlane(dcur[(k) / 64], (k) % 64)
+#define SDD_WORD(k) __builtin_amdgcn_readlane(dcur[(k) / 64], (k) % 64)
 
   const int32_t nstages = (nchan + CS - 1) / CS;
   const int32_t lane_off = 8 * lane + ES * TW * wt;  // bytes
-  const int32_t flush_every = ES == 1 ? 256 : a.flush;
+  const int32_t fstages = (ES == 1 ? 256 : a.flush) / CS;
+  int32_t fl = fstages;
   int32_t dnext[NDV];
-  int32_t dnext2[(PREF2 || EARLY) ? NDV : 1];
-  if constexpr (EARLY) {
-    load_delays(0, dnext);
-    load_stage_bases(0, st, dnext);
-    if (nstages > 1) load_delays(CS, dnext2);
-  } else {
-    load_stage(0, st);
-    load_delays(0, dnext);
-  }
-  store_stage(0, st);
-  if constexpr (PREF2) {
-    if (nstages > 1) {
-      load_stage(CS, st);
-      load_delays(CS, dnext2);
-    }
+  int32_t bnext[NLD];
+  {
+    int32_t b0[NLD];
+    load_bases(0, b0);
+    load_words(0);
+    load_data(0, b0);
+    if (nstages > 1) load_bases(1, bnext);
+    pack_words(dnext);
+    store_stage(0);
   }
   __syncthreads();
   for (int32_t s = 0; s < nstages; ++s) {
-    const int32_t cbase = s * CS;
     int32_t dcur[NDV];
 #pragma unroll
     for (int v = 0; v < NDV; ++v) dcur[v] = dnext[v];
-    if constexpr (EARLY) {
-      // stage s+1's delays arrived a stage ago: stage its data now, fetch
-      // the delays of stage s+2
-      if (s + 1 < nstages) load_stage_bases(cbase + CS, st, dnext2);
-#pragma unroll
-      for (int v = 0; v < NDV; ++v) dnext[v] = dnext2[v];
-      if (s + 2 < nstages) load_delays(cbase + 2 * CS, dnext2);
-    } else if constexpr (PREF2) {
-      // stage s+1 is in st (loaded one stage ago); fetch stage s+2
-      if (s + 2 < nstages) {
-        load_stage(cbase + 2 * CS, st2);
-        int32_t dtmp[NDV];
-        load_delays(cbase + 2 * CS, dtmp);
-#pragma unroll
-        for (int v = 0; v < NDV; ++v) {
-          dnext[v] = dnext2[v];
-          dnext2[v] = dtmp[v];
-        }
-      } else {
-#pragma unroll
-        for (int v = 0; v < NDV; ++v) dnext[v] = dnext2[v];
-      }
-    } else if (s + 1 < nstages) {
-      load_stage(cbase + CS, st);
-      load_delays(cbase + CS, dnext);
+    if (s + 1 < nstages) {
+      // stage s+1: data (its bases arrived a stage ago) and read positions;
+      // stage s+2: window bases
+      load_data(s + 1, bnext);
+      load_words(s + 1);
+      if (s + 2 < nstages) load_bases(s + 2, bnext);
     }
     const uint8_t* bufp = lds + (s & 1) * buf + lane_off;
 #pragma unroll
@@ -275,8 +244,8 @@ __device__ __forceinline__ void dd_tile(const LdsArgs a, int32_t dtile, int32_t 
       const uint8_t* slotB = slotA + slot;
 #pragma unroll
       for (int d = 0; d < D; ++d) {
-        const uint32_t wA = (uint32_t)SDD_DELAY(cc * DE + 1 + d);
-        const uint32_t wB = (uint32_t)SDD_DELAY((cc + 1) * DE + 1 + d);
+        const uint32_t wA = (uint32_t)SDD_WORD(cc * D + d);
+        const uint32_t wB = (uint32_t)SDD_WORD((cc + 1) * D + d);
         const int32_t adA = (int32_t)(wA & 0xfffffu);
         const int32_t adB = (int32_t)(wB & 0xfffffu);
         const uint32_t rA = wA >> 20, rB = wB >> 20;
@@ -323,16 +292,18 @@ __device__ __forceinline__ void dd_tile(const LdsArgs a, int32_t dtile, int32_t 
         }
       }
     }
-    if ((cbase + CS) % flush_every == 0 || s + 1 == nstages) flush();
-    if (s + 1 < nstages) store_stage((s + 1) & 1, st);
-    if constexpr (PREF2) {
-#pragma unroll
-      for (int k = 0; k < NLD; ++k) st[k] = st2[k];
+    if (--fl == 0 || s + 1 == nstages) {
+      flush();
+      fl = fstages;
+    }
+    if (s + 1 < nstages) {
+      store_stage((s + 1) & 1);
+      pack_words(dnext);
     }
     __syncthreads();
   }
 
-#undef SDD_DELAY
+#undef SDD_WORD
 
   // ---- store the tile ----
 #pragma unroll
@@ -355,6 +326,15 @@ __device__ __forceinline__ void dd_tile(const LdsArgs a, int32_t dtile, int32_t 
       }
     }
   }
+}
+
+template <int D, int M, int WD, int WT, int CS, int NLD, int F, int ES>
+__device__ __forceinline__ void dd_tile(const LdsArgs& a, int32_t dtile, int32_t ttile,
+                                        uint8_t* __restrict__ lds) {
+  if (ttile < a.n_tt_interior)
+    dd_tile_impl<D, M, WD, WT, CS, NLD, F, ES, true>(a, dtile, ttile, lds);
+  else
+    dd_tile_impl<D, M, WD, WT, CS, NLD, F, ES, false>(a, dtile, ttile, lds);
 }
 
 // Grid form: one workgroup per tile of one job, ordered DM-tile-major with a
@@ -445,20 +425,20 @@ hipError_t launch_one(const LdsArgs& a, hipStream_t s) {
 // The built menu, {D, M, WD, WT, CS, NLD, F}; sdd_tile carries it as
 // {kind 1 + F, D, WD, WT, pairs per lane = 4*M, CS}.
 #define SDD_LDS_SHAPES(X)      \
-  X(2, 2, 4, 1, 4, 2, 4)       \
-  X(2, 1, 4, 1, 4, 1, 4)       \
-  X(4, 1, 4, 1, 4, 2, 4)       \
-  X(4, 1, 2, 2, 4, 2, 4)       \
-  X(2, 2, 2, 1, 4, 3, 4)       \
-  X(4, 1, 2, 1, 4, 2, 4)       \
-  X(4, 1, 8, 1, 4, 1, 4)       \
-  X(4, 1, 4, 2, 4, 2, 4)       \
-  X(2, 1, 8, 1, 4, 1, 4)       \
-  X(4, 1, 16, 1, 4, 1, 4)      \
-  X(4, 1, 8, 2, 4, 1, 4)       \
+  X(2, 2, 8, 1, 4, 1, 0)       \
+  X(2, 2, 8, 1, 4, 1, 2)       \
+  X(2, 2, 4, 1, 4, 2, 0)       \
+  X(2, 2, 4, 1, 4, 2, 2)       \
+  X(2, 2, 8, 1, 8, 2, 0)       \
+  X(2, 1, 4, 1, 4, 1, 0)       \
+  X(4, 1, 4, 1, 4, 2, 0)       \
+  X(4, 1, 4, 1, 4, 2, 2)       \
+  X(4, 1, 2, 2, 4, 2, 0)       \
+  X(2, 2, 2, 1, 4, 3, 0)       \
+  X(4, 1, 8, 1, 4, 1, 0)       \
+  X(1, 4, 8, 1, 4, 2, 0)       \
   X(4, 1, 8, 2, 4, 1, 0)       \
-  X(4, 1, 8, 2, 4, 1, 1)       \
-  X(4, 1, 8, 2, 4, 1, 6)       \
+  X(4, 1, 16, 1, 4, 1, 0)      \
   X(8, 1, 4, 1, 8, 4, 0)
 
 #define SDD_SHAPE_ROW(d, m, wd, wt, cs, nld, f) {d, m, wd, wt, cs, nld, f},

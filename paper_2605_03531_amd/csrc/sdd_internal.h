@@ -160,6 +160,7 @@ struct DedispArgs {
   int32_t max_val;        // largest input value (255 * dec)
   sdd_tile tile;
   int32_t span;           // largest delay difference over a DM tile of the chosen shape
+  int32_t max_delay;      // largest delay of the range (samples of x)
 };
 hipError_t launch_dedisperse(const DedispArgs& a, hipStream_t s);
 
