@@ -78,10 +78,10 @@ __device__ __forceinline__ void dd_tile_impl(const LdsArgs& a, int32_t dtile, in
   // loads address (uniform stage base) + (32-bit per-lane offset); the
   // window starts at sample t0 + (d(c, i0) & ~15), with d(c, i0) loaded two
   // stages ahead by the element itself.
-  int32_t ecs[NLD];
+  int32_t ecs[NLD];     // slot, CS for an unused element
   uint32_t eoff[NLD];   // cs * pitch + 16 q (bytes from the stage's row base)
   int32_t eq16[NLD];    // 16 q
-  uint32_t ebase[NLD];  // cs * ndm (delay-table entries from the stage's first row)
+  uint32_t ebase[NLD];  // (cs * ndm + i0) * 4 (bytes from the stage's first delay row)
   int32_t elds[NLD];    // cs * slot + 16 q
 #pragma unroll
   for (int k = 0; k < NLD; ++k) {
@@ -89,61 +89,58 @@ __device__ __forceinline__ void dd_tile_impl(const LdsArgs& a, int32_t dtile, in
     const int32_t cs = e / wq;
     const int32_t q = e - cs * wq;
     ecs[k] = cs < CS ? cs : CS;
+    // an unused element loads (and never stores) a valid window of slot 0
     const int32_t csv = cs < CS ? cs : 0;
     eoff[k] = (uint32_t)(csv * pitch_bytes) + 16u * (uint32_t)q;
     eq16[k] = 16 * q;
-    ebase[k] = (uint32_t)(csv * ndm);
+    ebase[k] = 4u * (uint32_t)(csv * ndm + i0);
     elds[k] = csv * slot + 16 * q;
   }
   const uint8_t* __restrict__ xs = a.x + ES * t0;  // stage 0 row base (uniform)
-  const int32_t* __restrict__ ds = a.delays;       // stage 0 delay row base (uniform)
+  // stage 0 delay row base (uniform); the table has zero rows up to a
+  // multiple of kDelayRowPad channels, so every stage reads it unmasked
+  const uint8_t* __restrict__ ds = reinterpret_cast<const uint8_t*>(a.delays);
+  const int64_t stage_drow = 4 * (int64_t)CS * ndm;  // delay-table bytes per stage
+  static_assert(CS <= kDelayRowPad, "stage wider than the delay-table padding");
 
   uint4 st[NLD];
   uint32_t ext[NLD];
-  // d(c, i0) of each element's channel at a stage (0 past the last channel)
+  // d(c, i0) of each element's channel at a stage
   auto load_bases = [&](int32_t s, int32_t (&dst)[NLD]) {
-    const int32_t* row = ds + (int64_t)s * CS * ndm + i0;
+    const uint8_t* row = ds + (int64_t)s * stage_drow;
 #pragma unroll
-    for (int k = 0; k < NLD; ++k) {
-      const bool ok = ecs[k] < CS && s * CS + ecs[k] < nchan;
-      dst[k] = ok ? row[ebase[k]] : 0;
-    }
+    for (int k = 0; k < NLD; ++k) dst[k] = *reinterpret_cast<const int32_t*>(row + ebase[k]);
   };
+  // Stages cover whole groups of CS channels; the nchan % CS channels left
+  // over are added after the loop.
   auto load_data = [&](int32_t s, const int32_t (&bases)[NLD]) {
     const uint8_t* row = xs + (int64_t)s * CS * pitch_bytes;
 #pragma unroll
     for (int k = 0; k < NLD; ++k) {
-      const bool ok = ecs[k] < CS && s * CS + ecs[k] < nchan;
       const uint32_t off = eoff[k] + (uint32_t)(ES * (bases[k] & ~15));
-      uint4 v = make_uint4(0u, 0u, 0u, 0u);
-      uint32_t x4 = 0u;
-      if (ok) {
-        const uint8_t* src = row + off;
-        if constexpr (INTERIOR) {
-          v = *reinterpret_cast<const uint4*>(src);
-          x4 = *reinterpret_cast<const uint32_t*>(src + 16);
+      const uint8_t* src = row + off;
+      if constexpr (INTERIOR) {
+        st[k] = *reinterpret_cast<const uint4*>(src);
+        ext[k] = *reinterpret_cast<const uint32_t*>(src + 16);
+      } else {
+        // byte g of the row; zero past its end
+        const int64_t g = ES * (t0 + (bases[k] & ~15)) + eq16[k];
+        uint32_t w[5] = {0u, 0u, 0u, 0u, 0u};
+        if (a.aligned && g + 20 <= row_bytes) {
+          const uint4 t = *reinterpret_cast<const uint4*>(src);
+          w[0] = t.x; w[1] = t.y; w[2] = t.z; w[3] = t.w;
+          w[4] = *reinterpret_cast<const uint32_t*>(src + 16);
         } else {
-          // byte g of the row; zero past its end
-          const int64_t g = ES * (t0 + (bases[k] & ~15)) + eq16[k];
-          uint32_t w[5] = {0u, 0u, 0u, 0u, 0u};
-          if (a.aligned && g + 20 <= row_bytes) {
-            const uint4 t = *reinterpret_cast<const uint4*>(src);
-            w[0] = t.x; w[1] = t.y; w[2] = t.z; w[3] = t.w;
-            w[4] = *reinterpret_cast<const uint32_t*>(src + 16);
-          } else {
-            for (int bb = 0; bb < 20; ++bb)
-              if (g + bb < row_bytes) w[bb >> 2] |= (uint32_t)src[bb] << (8 * (bb & 3));
-          }
-          v = make_uint4(w[0], w[1], w[2], w[3]);
-          x4 = w[4];
+          for (int bb = 0; bb < 20; ++bb)
+            if (g + bb < row_bytes) w[bb >> 2] |= (uint32_t)src[bb] << (8 * (bb & 3));
         }
+        st[k] = make_uint4(w[0], w[1], w[2], w[3]);
+        ext[k] = w[4];
       }
-      st[k] = v;
-      ext[k] = x4;
     }
   };
-  auto store_stage = [&](int32_t which) {
-    uint8_t* base = lds + which * buf;
+  auto store_stage = [&](int32_t s) {
+    uint8_t* base = lds + (s & 1) * buf;
 #pragma unroll
     for (int k = 0; k < NLD; ++k) {
       if (ecs[k] < CS) {
@@ -176,26 +173,23 @@ __device__ __forceinline__ void dd_tile_impl(const LdsArgs& a, int32_t dtile, in
   // loop needs one v_readlane and a few scalar operations per channel and
   // trial, and no scalar-memory waits that would also drain its LDS reads.
   // A channel past nchan gets offset 0 into its all-zero window.
-  int32_t dl_cs[NDV];
-  uint32_t dl_off[NDV], dl_off0[NDV];
+  uint32_t dl_off[NDV], dl_off0[NDV];  // bytes from the stage's first delay row
 #pragma unroll
   for (int v = 0; v < NDV; ++v) {
     const int32_t k = 64 * v + lane;
     const int32_t cs = k / D, d = k - cs * D;
     const int32_t i = i0 + wd * D + d;
-    dl_cs[v] = k < CS * D ? cs : CS;
     const int32_t csv = k < CS * D ? cs : 0;
-    dl_off[v] = (uint32_t)(csv * ndm + (i < ndm ? i : ndm - 1));
-    dl_off0[v] = (uint32_t)(csv * ndm + i0);
+    dl_off[v] = 4u * (uint32_t)(csv * ndm + (i < ndm ? i : ndm - 1));
+    dl_off0[v] = 4u * (uint32_t)(csv * ndm + i0);
   }
   int32_t rdv[NDV], rd0[NDV];
   auto load_words = [&](int32_t s) {
-    const int32_t* row = ds + (int64_t)s * CS * ndm;
+    const uint8_t* row = ds + (int64_t)s * stage_drow;
 #pragma unroll
     for (int v = 0; v < NDV; ++v) {
-      const bool ok = dl_cs[v] < CS && s * CS + dl_cs[v] < nchan;
-      rdv[v] = ok ? row[dl_off[v]] : 0;
-      rd0[v] = ok ? row[dl_off0[v]] : 0;
+      rdv[v] = *reinterpret_cast<const int32_t*>(row + dl_off[v]);
+      rd0[v] = *reinterpret_cast<const int32_t*>(row + dl_off0[v]);
     }
   };
   auto pack_words = [&](int32_t (&out)[NDV]) {
@@ -210,13 +204,13 @@ __device__ __forceinline__ void dd_tile_impl(const LdsArgs& a, int32_t dtile, in
   // entry k of the current stage, as a wave-uniform scalar
 #define SDD_WORD(k) __builtin_amdgcn_readlane(dcur[(k) / 64], (k) % 64)
 
-  const int32_t nstages = (nchan + CS - 1) / CS;
+  const int32_t nstages = nchan / CS;  // whole stages
   const int32_t lane_off = 8 * lane + ES * TW * wt;  // bytes
   const int32_t fstages = (ES == 1 ? 256 : a.flush) / CS;
   int32_t fl = fstages;
   int32_t dnext[NDV];
   int32_t bnext[NLD];
-  {
+  if (nstages > 0) {
     int32_t b0[NLD];
     load_bases(0, b0);
     load_words(0);
@@ -291,19 +285,43 @@ __device__ __forceinline__ void dd_tile_impl(const LdsArgs& a, int32_t dtile, in
           }
         }
       }
+      // keep the scheduler from hoisting the LDS reads of more than four
+      // channels at once (their registers would cost occupancy)
+      if constexpr (CS > 4)
+        if ((cc & 3) == 2) __builtin_amdgcn_sched_barrier(0);
     }
     if (--fl == 0 || s + 1 == nstages) {
       flush();
       fl = fstages;
     }
     if (s + 1 < nstages) {
-      store_stage((s + 1) & 1);
+      store_stage(s + 1);
       pack_words(dnext);
     }
     __syncthreads();
   }
 
 #undef SDD_WORD
+
+  // ---- the nchan % CS channels past the last whole stage, from global ----
+  for (int32_t c = nstages * CS; c < nchan; ++c) {
+    const uint8_t* xrow = a.x + (int64_t)c * pitch_bytes;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const int32_t i = i0 + wd * D + d;
+      const int32_t dl = a.delays[(int64_t)c * ndm + (i < ndm ? i : ndm - 1)];
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        const int64_t j = t0 + TW * wt + CH * m + SPL * lane + dl;
+#pragma unroll
+        for (int k = 0; k < SPL; ++k) {
+          if (j + k < a.x_len)
+            wide[d][m][k] += ES == 1 ? (uint32_t)xrow[j + k]
+                                     : (uint32_t)reinterpret_cast<const uint16_t*>(xrow)[j + k];
+        }
+      }
+    }
+  }
 
   // ---- store the tile ----
 #pragma unroll

@@ -224,7 +224,7 @@ sdd_status plan_upload(const sdd_plan* p) {
   for (size_t r = 0; r < p->ranges.size(); ++r) {
     const Range& R = p->ranges[r];
     const int32_t ndm = R.ndm();
-    std::vector<int32_t> cm((size_t)ndm * C);
+    std::vector<int32_t> cm((size_t)ndm * round_up(C, kDelayRowPad), 0);
     for (int32_t i = 0; i < ndm; ++i)
       for (int32_t c = 0; c < C; ++c) cm[(size_t)c * ndm + i] = R.delays[(size_t)i * C + c];
     int32_t* d = nullptr;

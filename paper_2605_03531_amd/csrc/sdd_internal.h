@@ -34,6 +34,9 @@ void clear_error();
   } while (0)
 
 constexpr double kDispersionConstant = 4.148808e3;  // s MHz^2 pc^-1 cm^3
+// Device delay tables are padded with zero rows to a multiple of this many
+// channels, so a kernel stage of up to this many channels reads them unmasked.
+constexpr int32_t kDelayRowPad = 16;
 
 // Brackets one stage's launches with HIP events on its stream while timing is
 // enabled (sdd_profile_enable); does nothing otherwise.
@@ -106,7 +109,8 @@ struct sdd_plan {
   // device copies, made on first use
   mutable std::mutex mu;
   mutable int uploaded_device = -1;
-  mutable std::vector<int32_t*> d_delays;  // per range, [nchan][ndm_r]
+  // per range, [round_up(nchan, kDelayRowPad)][ndm_r]; rows past nchan are 0
+  mutable std::vector<int32_t*> d_delays;
   mutable int32_t* d_widths = nullptr;
 
   int32_t cells_for(int64_t n_owned_r) const {
