@@ -125,6 +125,7 @@ sdd_status run_search(const sdd_plan* p, const CallGeom& cg, const uint32_t* con
   a.cand_block = p->cand_block;
   a.threshold = p->threshold;
   a.cap = cap;
+  a.max_boxcar = (int64_t)p->nchan * 255 * p->dec_max * p->w_max;
   a.max_cells = 0;
   for (int32_t r = 0; r < a.nranges; ++r) {
     const Range& R = p->ranges[r];

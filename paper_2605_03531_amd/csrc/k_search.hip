@@ -1,9 +1,13 @@
 // Single-pulse search by time-domain boxcar filtering (Section 2.1) over the
 // dedispersed DM-time planes:
-//   k_cells    per (trial, cell of owned starts): wrap-around uint32 prefix
-//              sums in LDS give B_w[j] = P[j+w] - P[j] exactly; the maximum
-//              and first argmax per width; exact uint64 S1/S2 of the owned
-//              samples, accumulated per trial with integer atomics.
+//   k_seg      one wavefront per 1024 owned starts of one trial (cells of a
+//              multiple of 1024 starts): samples in registers, wrap-around
+//              uint32 prefix sums by a wave scan into LDS, B_w[j] = P[j+w] -
+//              P[j] exactly; per width the maximum and first argmax; exact
+//              uint64 S1/S2 of the owned samples, accumulated per trial with
+//              integer atomics.
+//   k_cells    the same per (trial, cell) for any cell size, one workgroup
+//              per cell (used when k_seg's layout conditions do not hold).
 //   k_rows     per trial: FP64 mean/sigma from the exact moments, S/N of each
 //              cell's per-width maxima, the cell's best, the trial's best and
 //              its candidate count (S/N > threshold).
@@ -11,6 +15,7 @@
 //   k_compact  per trial: writes its candidates in sample order at its offset.
 // Every step is deterministic: integer sums are order-free and every
 // selection has a total tie order.
+#include <algorithm>
 #include <cmath>
 
 #include "sdd_internal.h"
@@ -21,10 +26,9 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kSub = 1024;  // owned starts per LDS sub-segment
 
-struct CellRes {
-  uint32_t b;
-  int32_t j;
-};
+// Per (cell, width) result: (max B << 32) | ~(first argmax - cell start),
+// so the larger key is the larger sum, then the earlier start.
+using CellKey = unsigned long long;
 struct CellBest {
   double snr;
   int32_t j;
@@ -94,7 +98,7 @@ __global__ __launch_bounds__(kThreads) void k_cells(SearchArgs a) {
   const int32_t i = g - R.dm_offset;
   const uint32_t* row = R.plane + (int64_t)i * R.pitch;
   Moments* mom = reinterpret_cast<Moments*>(a.ws + a.moments_off);
-  CellRes* cres = reinterpret_cast<CellRes*>(a.ws + a.cellres_off);
+  CellKey* cres = reinterpret_cast<CellKey*>(a.ws + a.cellres_off);
   unsigned long long s1 = 0, s2 = 0;
   for (int32_t cell = blockIdx.y; cell < R.ncells; cell += gridDim.y) {
     const int64_t jb = (int64_t)cell * a.cand_block;
@@ -146,13 +150,8 @@ __global__ __launch_bounds__(kThreads) void k_cells(SearchArgs a) {
       }
     }
     __syncthreads();
-    if (tid < a.nwidths) {
-      const unsigned long long m = run_best[tid];
-      CellRes c;
-      c.b = (uint32_t)(m >> 32);
-      c.j = (int32_t)(jb + (int64_t)(~(uint32_t)m));
-      cres[(R.cell_base + (int64_t)i * R.ncells + cell) * a.nwidths + tid] = c;
-    }
+    if (tid < a.nwidths) cres[(R.cell_base + (int64_t)i * R.ncells + cell) * a.nwidths + tid] =
+        run_best[tid];
   }
   // exact moments of this block's owned samples
   s1 = wave_sum_u64(s1);
@@ -171,6 +170,206 @@ __global__ __launch_bounds__(kThreads) void k_cells(SearchArgs a) {
     }
     atomicAdd(&mom[g].s1, t1);
     atomicAdd(&mom[g].s2, t2);
+  }
+}
+
+constexpr int kSeg = 1024;         // owned starts per wavefront
+constexpr int kSegHaloMax = 1024;  // largest halo (w_max - 1, rounded up to 16)
+
+// 16 consecutive plane samples from index j (a multiple of 16); zero at and
+// past cols. Rows are 16-byte aligned (checked on the host).
+__device__ inline void load16(const uint32_t* row, int64_t j, int64_t cols, uint32_t (&y)[16]) {
+  if (j + 16 <= cols) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint4 v = *reinterpret_cast<const uint4*>(row + j + 4 * q);
+      y[4 * q] = v.x;
+      y[4 * q + 1] = v.y;
+      y[4 * q + 2] = v.z;
+      y[4 * q + 3] = v.w;
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < 16; ++t) y[t] = j + t < cols ? row[j + t] : 0u;
+  }
+}
+
+// Exclusive prefix of 16 values per lane over the wavefront: e[t] = carry +
+// sum of all earlier values; returns the wavefront total (wrap-around uint32).
+__device__ inline uint32_t wave_prefix16(const uint32_t (&y)[16], uint32_t carry, uint32_t (&e)[16]) {
+  const int lane = threadIdx.x & 63;
+  uint32_t run = 0;
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    e[t] = run;
+    run += y[t];
+  }
+  uint32_t inc = run;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t v = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += v;
+  }
+  const uint32_t off = carry + inc - run;
+#pragma unroll
+  for (int t = 0; t < 16; ++t) e[t] += off;
+  return __shfl(inc, 63, 64);
+}
+
+__device__ inline uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint32_t t = __shfl_xor(v, o, 64);
+    v = t > v ? t : v;
+  }
+  return v;
+}
+
+// E[16 l + t + w] for t < 16: aligned 128-bit LDS reads when w % 4 == 0.
+__device__ inline void read_shifted(const uint32_t* E, int lane, int w, uint32_t (&v)[16]) {
+  const uint32_t* p = E + 16 * lane + w;
+  if ((w & 3) == 0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint4 u = *reinterpret_cast<const uint4*>(p + 4 * q);
+      v[4 * q] = u.x;
+      v[4 * q + 1] = u.y;
+      v[4 * q + 2] = u.z;
+      v[4 * q + 3] = u.w;
+    }
+  } else if ((w & 1) == 0) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const uint2 u = *reinterpret_cast<const uint2*>(p + 2 * q);
+      v[2 * q] = u.x;
+      v[2 * q + 1] = u.y;
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < 16; ++t) v[t] = p[t];
+  }
+}
+
+// NARROW: every boxcar sum is below 2^28, so (B << 4) | (15 - t) orders by
+// sum, then by earlier start, and one v_max per start keeps both.
+template <bool NARROW>
+__global__ __launch_bounds__(64) void k_seg(SearchArgs a) {
+  extern __shared__ __attribute__((aligned(16))) uint32_t E[];  // kSeg + H + 4
+  const int lane = threadIdx.x;
+  const int32_t g = blockIdx.x;
+  const int r = find_range(a, g);
+  const SearchRange& R = a.r[r];
+  const int32_t i = g - R.dm_offset;
+  const int64_t n = R.n_owned;
+  const int64_t cols = n + a.w_max - 1;
+  const int32_t nseg = (int32_t)((n + kSeg - 1) / kSeg);
+  const uint32_t* row = R.plane + (int64_t)i * R.pitch;
+  const int32_t H = (a.w_max - 1 + 15) & ~15;  // halo samples
+  const int32_t segs_per_cell = a.cand_block / kSeg;
+  CellKey* cres = reinterpret_cast<CellKey*>(a.ws + a.cellres_off);
+  unsigned long long s1 = 0, s2 = 0;
+  for (int32_t seg = blockIdx.y; seg < nseg; seg += gridDim.y) {
+    const int64_t j0 = (int64_t)seg * kSeg;
+    const int64_t jl = j0 + 16 * lane;  // this lane's first start
+    const bool full = j0 + kSeg <= n;
+    uint32_t y[16], e[16];
+    load16(row, jl, cols, y);
+    if (full || jl + 16 <= n) {
+#pragma unroll
+      for (int t = 0; t < 16; ++t) {
+        s1 += y[t];
+        s2 += (unsigned long long)y[t] * y[t];
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < 16; ++t)
+        if (jl + t < n) {
+          s1 += y[t];
+          s2 += (unsigned long long)y[t] * y[t];
+        }
+    }
+    const uint32_t total = wave_prefix16(y, 0u, e);
+    __syncthreads();  // the previous segment's readers are done with E
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      *reinterpret_cast<uint4*>(E + 16 * lane + 4 * q) =
+          make_uint4(e[4 * q], e[4 * q + 1], e[4 * q + 2], e[4 * q + 3]);
+    if (H > 0) {
+      uint32_t h[16], he[16];
+      const bool hl = 16 * lane < H;
+      if (hl)
+        load16(row, j0 + kSeg + 16 * lane, cols, h);
+      else
+#pragma unroll
+        for (int t = 0; t < 16; ++t) h[t] = 0u;
+      const uint32_t htot = wave_prefix16(h, total, he);
+      if (hl)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          *reinterpret_cast<uint4*>(E + kSeg + 16 * lane + 4 * q) =
+              make_uint4(he[4 * q], he[4 * q + 1], he[4 * q + 2], he[4 * q + 3]);
+      if (lane == 0) E[kSeg + H] = total + htot;
+    } else if (lane == 0) {
+      E[kSeg] = total;
+    }
+    __syncthreads();
+    const bool lane_ok = jl < n;
+    const int32_t tmax = full ? 16 : (int32_t)min<int64_t>(16, n - jl);  // valid starts of this lane
+    const int32_t cell = seg / segs_per_cell;
+    const int64_t cstart = (int64_t)cell * a.cand_block;
+    for (int k = 0; k < a.nwidths; ++k) {
+      const int w = a.widths[k];
+      uint32_t v[16];
+      if (w == 1) {
+#pragma unroll
+        for (int t = 0; t < 16; ++t) v[t] = y[t];
+      } else {
+        read_shifted(E, lane, w, v);
+#pragma unroll
+        for (int t = 0; t < 16; ++t) v[t] -= e[t];
+      }
+      uint32_t bb, bt;
+      if constexpr (NARROW) {
+        uint32_t key = 0u;
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+          const uint32_t kt = (v[t] << 4) | (uint32_t)(15 - t);
+          if (full || t < tmax) key = kt > key ? kt : key;
+        }
+        bb = key >> 4;
+        bt = 15u - (key & 15u);
+      } else {
+        bb = v[0];
+        bt = 0u;
+#pragma unroll
+        for (int t = 1; t < 16; ++t)
+          if ((full || t < tmax) && v[t] > bb) {
+            bb = v[t];
+            bt = (uint32_t)t;
+          }
+      }
+      if (!lane_ok) bb = 0u;
+      const uint32_t m = wave_max_u32(bb);
+      const unsigned long long hit = __ballot(lane_ok && bb == m);
+      const int f = __builtin_ctzll(hit);
+      const uint32_t tf = __shfl(bt, f, 64);
+      if (lane == 0) {
+        const int64_t j = j0 + 16 * f + tf;
+        const CellKey key = ((CellKey)m << 32) | (uint32_t)(~(uint32_t)(j - cstart));
+        CellKey* dst = cres + (R.cell_base + (int64_t)i * R.ncells + cell) * a.nwidths + k;
+        if (segs_per_cell == 1)
+          *dst = key;
+        else
+          atomicMax(dst, key);
+      }
+    }
+  }
+  s1 = wave_sum_u64(s1);
+  s2 = wave_sum_u64(s2);
+  if (lane == 0) {
+    Moments* mom = reinterpret_cast<Moments*>(a.ws + a.moments_off);
+    atomicAdd(&mom[g].s1, s1);
+    atomicAdd(&mom[g].s2, s2);
   }
 }
 
@@ -193,7 +392,7 @@ __global__ __launch_bounds__(kThreads) void k_rows(SearchArgs a) {
   const SearchRange& R = a.r[r];
   const int32_t i = g - R.dm_offset;
   const Moments m = reinterpret_cast<const Moments*>(a.ws + a.moments_off)[g];
-  const CellRes* cres = reinterpret_cast<const CellRes*>(a.ws + a.cellres_off);
+  const CellKey* cres = reinterpret_cast<const CellKey*>(a.ws + a.cellres_off);
   CellBest* cbest = reinterpret_cast<CellBest*>(a.ws + a.cellbest_off);
   const uint64_t n = (uint64_t)R.n_owned;
   // D = n*S2 - S1^2 exactly (128-bit), sigma = sqrt(D)/n
@@ -223,7 +422,8 @@ __global__ __launch_bounds__(kThreads) void k_rows(SearchArgs a) {
   const double thr = (double)a.threshold;
   for (int32_t c = tid; c < R.ncells; c += kThreads) {
     const int64_t cidx = R.cell_base + (int64_t)i * R.ncells + c;
-    const CellRes* cr = cres + cidx * a.nwidths;
+    const CellKey* cr = cres + cidx * a.nwidths;
+    const int64_t cstart = (int64_t)c * a.cand_block;
     double cs;
     int64_t cj;
     int cw;
@@ -237,10 +437,13 @@ __global__ __launch_bounds__(kThreads) void k_rows(SearchArgs a) {
       cw = 0;
       for (int k = 0; k < a.nwidths; ++k) {
         const int w = a.widths[k];
-        const double s = ((double)cr[k].b - (double)w * mu) / (sigma * sqrt((double)w));
-        if (better(s, cr[k].j, w, cs, cj, cw)) {
+        const CellKey key = cr[k];
+        const uint32_t b = (uint32_t)(key >> 32);
+        const int64_t j = cstart + (int64_t)(~(uint32_t)key);
+        const double s = ((double)b - (double)w * mu) / (sigma * sqrt((double)w));
+        if (better(s, j, w, cs, cj, cw)) {
           cs = s;
-          cj = cr[k].j;
+          cj = j;
           cw = w;
         }
       }
@@ -355,9 +558,35 @@ hipError_t launch_search(const SearchArgs& a, hipStream_t s) {
   const int64_t nm = 2 * (int64_t)a.ndm_total;
   hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)((nm + 255) / 256)), dim3(256), 0, s,
                      reinterpret_cast<unsigned long long*>(a.ws + a.moments_off), nm);
-  const unsigned gy = (unsigned)(a.max_cells < 1 ? 1 : (a.max_cells > 65535 ? 65535 : a.max_cells));
-  const size_t lds = (size_t)(kSub + a.w_max) * sizeof(uint32_t);
-  hipLaunchKernelGGL(k_cells, dim3((unsigned)a.ndm_total, gy), dim3(kThreads), lds, s, a);
+  const int32_t halo = (a.w_max - 1 + 15) & ~15;
+  bool seg_ok = a.nwidths > 0 && a.cand_block % kSeg == 0 && halo <= kSegHaloMax;
+  int64_t max_owned = 0;
+  for (int r = 0; r < a.nranges; ++r) {
+    seg_ok = seg_ok && (uintptr_t)a.r[r].plane % 16 == 0 && a.r[r].pitch % 4 == 0;
+    max_owned = std::max(max_owned, a.r[r].n_owned);
+  }
+  if (seg_ok) {
+    const int64_t nseg = (max_owned + kSeg - 1) / kSeg;
+    if (a.cand_block > kSeg) {
+      // cells of several segments combine their keys with atomic max
+      int64_t ncell = 0;
+      for (int r = 0; r < a.nranges; ++r) ncell += (int64_t)a.r[r].ndm * a.r[r].ncells;
+      const int64_t nk = ncell * a.nwidths;
+      hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0, s,
+                         reinterpret_cast<unsigned long long*>(a.ws + a.cellres_off), nk);
+    }
+    const unsigned gy = (unsigned)std::max<int64_t>(1, std::min<int64_t>(nseg, 65535));
+    const size_t lds = (size_t)(kSeg + halo + 4) * sizeof(uint32_t);
+    if (a.max_boxcar < ((int64_t)1 << 28))
+      hipLaunchKernelGGL(k_seg<true>, dim3((unsigned)a.ndm_total, gy), dim3(64), lds, s, a);
+    else
+      hipLaunchKernelGGL(k_seg<false>, dim3((unsigned)a.ndm_total, gy), dim3(64), lds, s, a);
+  } else {
+    const unsigned gy =
+        (unsigned)(a.max_cells < 1 ? 1 : (a.max_cells > 65535 ? 65535 : a.max_cells));
+    const size_t lds = (size_t)(kSub + a.w_max) * sizeof(uint32_t);
+    hipLaunchKernelGGL(k_cells, dim3((unsigned)a.ndm_total, gy), dim3(kThreads), lds, s, a);
+  }
   hipLaunchKernelGGL(k_rows, dim3((unsigned)a.ndm_total), dim3(kThreads), 0, s, a);
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, a);
   hipLaunchKernelGGL(k_compact, dim3((unsigned)a.ndm_total), dim3(kThreads), 0, s, a);

@@ -189,6 +189,7 @@ struct SearchArgs {
   float threshold;
   int32_t max_cells;     // max_r ncells_r
   int32_t cap;
+  int64_t max_boxcar;    // bound on any boxcar sum: nchan * 255 * dec_max * w_max
   uint8_t* ws;           // workspace base
   int64_t cellres_off, moments_off, cellbest_off, rowcnt_off, rowoff_off;
   sdd_dm_best* best;

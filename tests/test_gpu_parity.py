@@ -47,6 +47,38 @@ def test_tiny_full_plane_and_search(tiny, layout):
     assert k == 100 and int(best[k]["sample"]) == 3000 and int(best[k]["width"]) == 4
 
 
+@pytest.mark.parametrize("case", ["narrow_1024", "narrow_2048", "wide_halo"])
+def test_segment_search_layouts(case):
+    """The search with cells of whole 1024-start segments: odd and even
+    widths (32-, 64- and 128-bit shifted reads of the prefix sums), a partial
+    last segment, cells of two segments (combined by atomic max), and a halo
+    of 1008 samples with boxcar bounds past 2^28 (the compare-and-select
+    path instead of packed keys)."""
+    if case == "wide_halo":
+        f = np.linspace(500.0, 300.0, 200)
+        ranges = [(0.0, 10.0, 1.0, 1), (10.0, 30.0, 2.0, 8)]
+        kw = dict(freqs_mhz=f, t_samp=1e-3, ranges=ranges, widths=[1, 7, 100, 1000],
+                  cand_block=1024, threshold=4.0)
+        nown, dm_pulse = 9000, 4.0
+    else:
+        f = np.linspace(500.0, 300.0, 64)
+        kw = dict(freqs_mhz=f, t_samp=1e-3, dm_list=np.arange(0.0, 51.0),
+                  widths=[1, 2, 3, 5, 8, 12, 16, 64],
+                  cand_block=1024 if case == "narrow_1024" else 2048, threshold=4.0)
+        nown, dm_pulse = 5000, 30.0
+    say(f"segment search case {case}")
+    spec = oracle_plan(kw)
+    T = spec.overlap + nown
+    x = synth.filterbank(41, len(f), T, 100.0, 20.0)
+    synth.inject_pulse(x, oracle.delay_table(f, [dm_pulse], 1e-3)[0], 2100, 5, 15.0)
+    orc = oracle.run(spec, x)
+    plan = _make(kw, "chan")
+    ph, res, g = gpu_run(plan, x)
+    compare_rows(spec, ph, orc)
+    rel = compare_search(spec, res, orc, full_rows=True)
+    say(f"max S/N rel err {rel:.2e}, candidates {res[3]}")
+
+
 def test_tiny_plane_only_and_determinism(tiny):
     kw = dict(freqs_mhz=tiny.freqs_mhz, t_samp=tiny.t_samp, dm_list=tiny.dm_list)
     plan = _make(kw)
@@ -200,32 +232,38 @@ def _menu_tiles():
 
 def test_every_tile_shape_is_exact():
     """Each kernel shape of the built menu gives the oracle's plane on a
-    ragged case: 999 channels (odd: the last channel has no partner in its
-    pair), 300 trials (a partial DM tile), a partial time tile and a padded
-    spectra pitch."""
+    ragged case: 999 channels (odd, and not a multiple of any stage, so the
+    last channels are added past the staged loop), 300 trials (a partial DM
+    tile), a partial time tile and a padded spectra pitch. A wide DM range
+    exercises large delay spans; a narrow one fits the shapes whose staging
+    holds only small spans, so every shape runs on at least one of them."""
     f = np.linspace(750.0, 550.0, 999)
-    dms = np.linspace(0.0, 300.0, 300)
-    kw = dict(freqs_mhz=f, t_samp=81.92e-6, dm_list=dms)
-    spec = oracle_plan(kw)
-    T = spec.overlap + 3 * 1024 + 77
-    x = synth.filterbank(31, 999, T, 128.0, 16.0)
-    rows = [0, 1, 63, 64, 150, 255, 256, 298, 299]
-    (_, yo, _), = oracle.run(spec, x, rows=[rows], search=False)
-    plan = _make(kw, "time")
-    seen = []
-    for tile in _menu_tiles():
-        try:
-            plan.set_tile(tile)
-        except Exception:
-            say(f"tile {tile} does not fit this plan")
-            continue
-        say(f"tile {tile}")
-        ph, _, g = gpu_run(plan, x, search=False, time_major=True)
-        assert (ph[0][rows].astype(np.int64) == yo).all(), tile
-        seen.append(ph[0])
-    assert len(seen) >= 3
-    for p in seen[1:]:
-        assert (p == seen[0]).all()
+    ran = set()
+    for dm_hi in (300.0, 12.0):
+        dms = np.linspace(0.0, dm_hi, 300)
+        kw = dict(freqs_mhz=f, t_samp=81.92e-6, dm_list=dms)
+        spec = oracle_plan(kw)
+        T = spec.overlap + 3 * 1024 + 77
+        x = synth.filterbank(31, 999, T, 128.0, 16.0)
+        rows = [0, 1, 63, 64, 150, 255, 256, 298, 299]
+        (_, yo, _), = oracle.run(spec, x, rows=[rows], search=False)
+        plan = _make(kw, "time")
+        seen = []
+        for tile in _menu_tiles():
+            try:
+                plan.set_tile(tile)
+            except Exception:
+                say(f"DM 0-{dm_hi}: tile {tile} does not fit this plan")
+                continue
+            say(f"DM 0-{dm_hi}: tile {tile}")
+            ph, _, g = gpu_run(plan, x, search=False, time_major=True)
+            assert (ph[0][rows].astype(np.int64) == yo).all(), tile
+            seen.append(ph[0])
+            ran.add(tuple(tile))
+        assert len(seen) >= 3
+        for p in seen[1:]:
+            assert (p == seen[0]).all()
+    assert ran == {tuple(t) for t in _menu_tiles()}
 
 
 def test_lds_tiles_on_channel_major_unaligned_input():
