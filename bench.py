@@ -216,7 +216,8 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--cpu-rows", type=int, default=8)
+    ap.add_argument("--cpu-rows", type=int, default=48,
+                    help="DM trials of the oracle's bounded CPU sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the streaming-server run")
     ap.add_argument("--serve-beams", type=int, default=160)
@@ -225,6 +226,9 @@ def main() -> int:
     ap.add_argument("--serve-batch", type=int, default=16)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-beams run")
     ap.add_argument("--batch-beams", type=int, default=32)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed steps, copy 1 GiB device-to-device three times "
+                         "(a kernel of known traffic for scaling HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: beams shard across GPUs with no exchange, so "
@@ -304,6 +308,14 @@ def main() -> int:
                      "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": None},
         "cpu_baseline": None,
     }
+    if args.copy_calibration:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev).fill_(7)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 x 1 GiB device copies (1 GiB read + 1 GiB written each)")
+        del src, dst
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample")
         res["cpu_baseline"] = cpu_baseline(w, plan.delays(0), args.cpu_rows)

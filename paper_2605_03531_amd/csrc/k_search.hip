@@ -194,35 +194,52 @@ __device__ inline void load16(const uint32_t* row, int64_t j, int64_t cols, uint
   }
 }
 
+// DPP lane moves within a wavefront (VALU, no LDS): row_shr:n shifts by n
+// lanes inside each row of 16 (lanes without a source read 0);
+// row_bcast:15 / :31 pass lane 15 of each row / lane 31 to the following
+// rows selected by the row mask.
+template <int CTRL, int ROWS>
+__device__ inline uint32_t dpp(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xf, false);
+}
+
+// Inclusive prefix sum over the 64 lanes (wrap-around uint32).
+__device__ inline uint32_t wave_incl_sum(uint32_t v) {
+  v += dpp<0x111, 0xf>(v);  // row_shr:1
+  v += dpp<0x112, 0xf>(v);  // row_shr:2
+  v += dpp<0x114, 0xf>(v);  // row_shr:4
+  v += dpp<0x118, 0xf>(v);  // row_shr:8
+  v += dpp<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+  return v;
+}
+
+// Maximum over the 64 lanes, returned to every lane.
+__device__ inline uint32_t wave_max_u32(uint32_t v) {
+  uint32_t t;
+  t = dpp<0x111, 0xf>(v); v = t > v ? t : v;
+  t = dpp<0x112, 0xf>(v); v = t > v ? t : v;
+  t = dpp<0x114, 0xf>(v); v = t > v ? t : v;
+  t = dpp<0x118, 0xf>(v); v = t > v ? t : v;
+  t = dpp<0x142, 0xa>(v); v = t > v ? t : v;
+  t = dpp<0x143, 0xc>(v); v = t > v ? t : v;
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
 // Exclusive prefix of 16 values per lane over the wavefront: e[t] = carry +
 // sum of all earlier values; returns the wavefront total (wrap-around uint32).
 __device__ inline uint32_t wave_prefix16(const uint32_t (&y)[16], uint32_t carry, uint32_t (&e)[16]) {
-  const int lane = threadIdx.x & 63;
   uint32_t run = 0;
 #pragma unroll
   for (int t = 0; t < 16; ++t) {
     e[t] = run;
     run += y[t];
   }
-  uint32_t inc = run;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t v = __shfl_up(inc, o, 64);
-    if (lane >= o) inc += v;
-  }
+  const uint32_t inc = wave_incl_sum(run);
   const uint32_t off = carry + inc - run;
 #pragma unroll
   for (int t = 0; t < 16; ++t) e[t] += off;
-  return __shfl(inc, 63, 64);
-}
-
-__device__ inline uint32_t wave_max_u32(uint32_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const uint32_t t = __shfl_xor(v, o, 64);
-    v = t > v ? t : v;
-  }
-  return v;
+  return (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
 }
 
 // E[16 l + t + w] for t < 16: aligned 128-bit LDS reads when w % 4 == 0.
@@ -267,6 +284,11 @@ __global__ __launch_bounds__(64) void k_seg(SearchArgs a) {
   const int32_t H = (a.w_max - 1 + 15) & ~15;  // halo samples
   const int32_t segs_per_cell = a.cand_block / kSeg;
   CellKey* cres = reinterpret_cast<CellKey*>(a.ws + a.cellres_off);
+  // lane k holds width k: the width loop reads it with v_readlane instead of
+  // a scalar load (whose wait would also drain the LDS reads)
+  const int32_t wlane = lane < a.nwidths ? a.widths[lane] : 0;
+  const int32_t nwidths = a.nwidths;
+  const int64_t cres_row = (R.cell_base + (int64_t)i * R.ncells) * nwidths;
   unsigned long long s1 = 0, s2 = 0;
   for (int32_t seg = blockIdx.y; seg < nseg; seg += gridDim.y) {
     const int64_t j0 = (int64_t)seg * kSeg;
@@ -275,11 +297,18 @@ __global__ __launch_bounds__(64) void k_seg(SearchArgs a) {
     uint32_t y[16], e[16];
     load16(row, jl, cols, y);
     if (full || jl + 16 <= n) {
+      if constexpr (NARROW) {
+        // samples are below 2^28 / w_max <= 2^28: 16 of them fit 32 bits
+        uint32_t p = 0;
 #pragma unroll
-      for (int t = 0; t < 16; ++t) {
-        s1 += y[t];
-        s2 += (unsigned long long)y[t] * y[t];
+        for (int t = 0; t < 16; ++t) p += y[t];
+        s1 += p;
+      } else {
+#pragma unroll
+        for (int t = 0; t < 16; ++t) s1 += y[t];
       }
+#pragma unroll
+      for (int t = 0; t < 16; ++t) s2 += (unsigned long long)y[t] * y[t];
     } else {
 #pragma unroll
       for (int t = 0; t < 16; ++t)
@@ -289,11 +318,14 @@ __global__ __launch_bounds__(64) void k_seg(SearchArgs a) {
         }
     }
     const uint32_t total = wave_prefix16(y, 0u, e);
+    // NARROW: LDS holds 16 * P, so 16 * P[j+w] - (16 * P[j] - (15 - t)) is
+    // the packed key (B << 4) | (15 - t) in one subtraction
+    constexpr int SH = NARROW ? 4 : 0;
     __syncthreads();  // the previous segment's readers are done with E
 #pragma unroll
     for (int q = 0; q < 4; ++q)
       *reinterpret_cast<uint4*>(E + 16 * lane + 4 * q) =
-          make_uint4(e[4 * q], e[4 * q + 1], e[4 * q + 2], e[4 * q + 3]);
+          make_uint4(e[4 * q] << SH, e[4 * q + 1] << SH, e[4 * q + 2] << SH, e[4 * q + 3] << SH);
     if (H > 0) {
       uint32_t h[16], he[16];
       const bool hl = 16 * lane < H;
@@ -307,22 +339,27 @@ __global__ __launch_bounds__(64) void k_seg(SearchArgs a) {
 #pragma unroll
         for (int q = 0; q < 4; ++q)
           *reinterpret_cast<uint4*>(E + kSeg + 16 * lane + 4 * q) =
-              make_uint4(he[4 * q], he[4 * q + 1], he[4 * q + 2], he[4 * q + 3]);
-      if (lane == 0) E[kSeg + H] = total + htot;
+              make_uint4(he[4 * q] << SH, he[4 * q + 1] << SH, he[4 * q + 2] << SH,
+                         he[4 * q + 3] << SH);
+      if (lane == 0) E[kSeg + H] = (total + htot) << SH;
     } else if (lane == 0) {
-      E[kSeg] = total;
+      E[kSeg] = total << SH;
+    }
+    if constexpr (NARROW) {
+#pragma unroll
+      for (int t = 0; t < 16; ++t) e[t] = (e[t] << 4) - (uint32_t)(15 - t);
     }
     __syncthreads();
     const bool lane_ok = jl < n;
     const int32_t tmax = full ? 16 : (int32_t)min<int64_t>(16, n - jl);  // valid starts of this lane
     const int32_t cell = seg / segs_per_cell;
     const int64_t cstart = (int64_t)cell * a.cand_block;
-    for (int k = 0; k < a.nwidths; ++k) {
-      const int w = a.widths[k];
+    for (int k = 0; k < nwidths; ++k) {
+      const int w = __builtin_amdgcn_readlane(wlane, k);
       uint32_t v[16];
       if (w == 1) {
 #pragma unroll
-        for (int t = 0; t < 16; ++t) v[t] = y[t];
+        for (int t = 0; t < 16; ++t) v[t] = NARROW ? (y[t] << 4) | (uint32_t)(15 - t) : y[t];
       } else {
         read_shifted(E, lane, w, v);
 #pragma unroll
@@ -330,11 +367,15 @@ __global__ __launch_bounds__(64) void k_seg(SearchArgs a) {
       }
       uint32_t bb, bt;
       if constexpr (NARROW) {
+        // v[t] is the key of start t
         uint32_t key = 0u;
+        if (full) {
 #pragma unroll
-        for (int t = 0; t < 16; ++t) {
-          const uint32_t kt = (v[t] << 4) | (uint32_t)(15 - t);
-          if (full || t < tmax) key = kt > key ? kt : key;
+          for (int t = 0; t < 16; t += 2) key = max(key, max(v[t], v[t + 1]));
+        } else {
+#pragma unroll
+          for (int t = 0; t < 16; ++t)
+            if (t < tmax) key = max(key, v[t]);
         }
         bb = key >> 4;
         bt = 15u - (key & 15u);
@@ -352,11 +393,11 @@ __global__ __launch_bounds__(64) void k_seg(SearchArgs a) {
       const uint32_t m = wave_max_u32(bb);
       const unsigned long long hit = __ballot(lane_ok && bb == m);
       const int f = __builtin_ctzll(hit);
-      const uint32_t tf = __shfl(bt, f, 64);
+      const uint32_t tf = (uint32_t)__builtin_amdgcn_readlane((int)bt, f);
       if (lane == 0) {
         const int64_t j = j0 + 16 * f + tf;
         const CellKey key = ((CellKey)m << 32) | (uint32_t)(~(uint32_t)(j - cstart));
-        CellKey* dst = cres + (R.cell_base + (int64_t)i * R.ncells + cell) * a.nwidths + k;
+        CellKey* dst = cres + cres_row + (int64_t)cell * nwidths + k;
         if (segs_per_cell == 1)
           *dst = key;
         else
@@ -575,7 +616,10 @@ hipError_t launch_search(const SearchArgs& a, hipStream_t s) {
       hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0, s,
                          reinterpret_cast<unsigned long long*>(a.ws + a.cellres_off), nk);
     }
-    const unsigned gy = (unsigned)std::max<int64_t>(1, std::min<int64_t>(nseg, 65535));
+    // a few segments per workgroup (a grid-stride loop) amortize its set-up
+    const int64_t per_wg = std::max<int64_t>(1, std::min<int64_t>(4, nseg / 64));
+    const unsigned gy =
+        (unsigned)std::max<int64_t>(1, std::min<int64_t>((nseg + per_wg - 1) / per_wg, 65535));
     const size_t lds = (size_t)(kSeg + halo + 4) * sizeof(uint32_t);
     if (a.max_boxcar < ((int64_t)1 << 28))
       hipLaunchKernelGGL(k_seg<true>, dim3((unsigned)a.ndm_total, gy), dim3(64), lds, s, a);
