@@ -35,6 +35,10 @@ WIDTHS = [1, 2, 4, 8, 16, 32, 64]
 # (v_pk_add_u16 / v_add3_u32), which is also one input byte per add from LDS
 # at 128 B/clk/CU
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 * 2 / 1e12
+# HBM bytes of one dedispersion launch of this workload, from rocprofv3 FETCH_SIZE /
+# WRITE_SIZE scaled by a copy kernel of known size (profiles/k_dedisp_lds_full_band_hbm_bytes.md).
+# Valid for the tile shape it was taken with; any other shape reports null.
+MEASURED_TRAFFIC = {"tile": [1, 2, 8, 1, 8, 4], "bytes": 52.97e9}
 
 
 def log(*a):
@@ -74,7 +78,7 @@ def cpu_baseline(w, plan_delays, rows: int):
 
 
 def serve_bench(sdd, torch, nbeams: int, sat_chunks: int, rt_periods: int, max_batch: int,
-                nstreams: int):
+                nstreams: int, per_item: bool = True):
     """Streaming server with nbeams beams (1024/2048/4096 channels by beam
     index mod 3), 2^16-sample chunks, 2048 DM trials 0-1000, widths 1..64.
 
@@ -100,7 +104,7 @@ def serve_bench(sdd, torch, nbeams: int, sat_chunks: int, rt_periods: int, max_b
 
     def run(chunks_per_beam, realtime, measure_from):
         srv = sdd.Server(hbm_budget=250 << 30, max_beams=nbeams, nstreams=nstreams,
-                         max_batch=max_batch, ring_chunks=2, cap=4096)
+                         max_batch=max_batch, ring_chunks=2, cap=4096, per_item=per_item)
         streams = [srv.open(plans[beam_c[b]], N, tag=b) for b in range(nbeams)]
         events = []
         for b in range(nbeams):
@@ -143,6 +147,7 @@ def serve_bench(sdd, torch, nbeams: int, sat_chunks: int, rt_periods: int, max_b
     out = {"beams": nbeams, "chunk_samples": N, "chunk_seconds": round(period, 4),
            "channel_mix": "1024/2048/4096 by beam index mod 3", "ndm": 2048, "widths": WIDTHS,
            "max_batch": max_batch, "slots": nstreams,
+           "batch_launch": "one grid launch per chunk" if per_item else "persistent multi-chunk",
            "saturated": {"chunks_per_beam": sat_chunks, "results": outputs,
                          "wall_s": round(wall, 3), "real_time_beams_capacity": round(capacity, 1),
                          "rtf_per_beam": round(capacity / nbeams, 3)}}
@@ -305,16 +310,21 @@ def main() -> int:
         "stage_ms": {k: round(v[0], 4) for k, v in stage.items()},
         "roofline": {"bound": "alu", "kernel": "dedisperse", "achieved": round(achieved, 3),
                      "peak": round(ALU_PEAK_TOPS, 1), "unit": "TOP/s",
-                     "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": None},
+                     "frac": round(achieved / ALU_PEAK_TOPS, 4),
+                     "traffic": (MEASURED_TRAFFIC["bytes"]
+                                 if list(plan.get_tile(0)) == MEASURED_TRAFFIC["tile"] else None)},
         "cpu_baseline": None,
     }
     if args.copy_calibration:
         src = torch.empty(1 << 30, dtype=torch.uint8, device=dev).fill_(7)
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            dst.copy_(src)                     # runtime copy kernel
+        for _ in range(3):
+            torch.bitwise_not(src, out=dst)    # elementwise kernel, same traffic
         torch.cuda.synchronize()
-        log("copy calibration: 3 x 1 GiB device copies (1 GiB read + 1 GiB written each)")
+        log("copy calibration: 3 x 1 GiB device copies and 3 x 1 GiB elementwise "
+            "(1 GiB read + 1 GiB written each)")
         del src, dst
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample")

@@ -281,10 +281,13 @@ enum {
 sdd_status sdd_batch_workspace_size(const sdd_batch_item* items, int32_t n, int64_t* bytes);
 /* Dedisperses and searches every item (Section 2.1 over many beams, the
  * beam-level parallelism of Section 2.2). By default the dedispersion of all
- * items whose DM ranges share an LDS tile shape runs as one persistent launch
- * whose workgroups pull tiles from per-XCD queues, so beams of uneven length
- * leave no tail per beam. Results equal per-item sdd_dedisperse_search calls
- * bit for bit. A graph replay (SDD_BATCH_GRAPH) re-runs the captured launches
+ * items whose DM ranges share an LDS tile shape runs as one persistent launch:
+ * the tile list is cut into one contiguous part per XCD and that XCD's
+ * workgroups walk it in rounds, so beams of uneven length leave no tail per
+ * beam. With SDD_BATCH_PER_ITEM every (chunk, range) is its own grid launch;
+ * for chunks of 2^16 samples or more this is the faster mode on MI355X (two
+ * or more streams then overlap one launch's tail with the next). Results
+ * equal per-item sdd_dedisperse_search calls bit for bit. A graph replay (SDD_BATCH_GRAPH) re-runs the captured launches
  * on the same buffers: the caller rewrites inputs in place between calls. */
 sdd_status sdd_batch_dedisperse_search(const sdd_batch_item* items, int32_t n, int32_t flags,
                                        void* d_ws, int64_t ws_bytes, void* stream);
@@ -308,7 +311,7 @@ typedef struct sdd_server_desc {
   int32_t max_batch;      /* output chunks per batch, 1..256 */
   int32_t ring_chunks;    /* ring depth beyond the overlap, in chunks (>= 2) */
   int32_t cap;            /* candidates kept per output chunk */
-  int32_t batch_flags;    /* SDD_BATCH_PER_ITEM or 0 (persistent launch) */
+  int32_t batch_flags;    /* SDD_BATCH_PER_ITEM (recommended) or 0 (persistent launch) */
   int32_t flags;          /* SDD_SERVER_FAKE */
   int32_t fake_exec_us;   /* batch duration in fake mode */
   int32_t reserved;

@@ -13,8 +13,7 @@
 
 namespace sdd {
 
-sdd_status launch_jobs_persistent(const std::vector<DedispArgs>& jobs, uint32_t* counters,
-                                  hipStream_t s) {
+sdd_status launch_jobs_persistent(const std::vector<DedispArgs>& jobs, hipStream_t s) {
   std::vector<LdsArgs> la(jobs.size());
   std::vector<int> shape(jobs.size());
   for (size_t i = 0; i < jobs.size(); ++i) shape[i] = lds_args_for(jobs[i], &la[i]);
@@ -40,7 +39,6 @@ sdd_status launch_jobs_persistent(const std::vector<DedispArgs>& jobs, uint32_t*
     }
     m.tile_base[n] = tiles;
     m.njobs = n;
-    m.counters = counters;
     SDD_HIP_TRY(launch_dedisperse_lds_multi(m, max_win, shape[i], s));
   }
   return SDD_OK;
@@ -54,7 +52,7 @@ sdd_status batch_layout(const BatchJob* items, int32_t n, std::vector<ItemGeom>*
                         int64_t* total) {
   if (!items || n < 1) SDD_FAIL(SDD_EINVAL, "empty batch");
   out->assign(n, ItemGeom{});
-  int64_t off = kCounterBytes;
+  int64_t off = 0;
   for (int32_t k = 0; k < n; ++k) {
     const sdd_batch_item& it = items[k].it;
     if (!it.plan) SDD_FAIL(SDD_EINVAL, "item %d: null plan", k);
@@ -144,7 +142,7 @@ sdd_status enqueue_batch(const BatchJob* items, int32_t n, int32_t flags,
   }
   if (!(flags & SDD_BATCH_PER_ITEM)) {
     StageTimer tm(SDD_STAGE_DEDISPERSE, s);
-    sdd_status st = launch_jobs_persistent(jobs, reinterpret_cast<uint32_t*>(ws), s);
+    sdd_status st = launch_jobs_persistent(jobs, s);
     if (st != SDD_OK) return st;
   }
   for (int32_t k = 0; k < n; ++k) {

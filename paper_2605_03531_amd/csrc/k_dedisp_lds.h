@@ -53,7 +53,6 @@ struct MultiArgs {
   LdsArgs jobs[kMaxJobs];
   int32_t tile_base[kMaxJobs + 1];  // first global tile of each job; [njobs] = total
   int32_t njobs;
-  uint32_t* counters;               // 8 device counters, one per XCD
 };
 
 hipError_t launch_dedisperse_lds(const LdsArgs& a, int shape, hipStream_t s);

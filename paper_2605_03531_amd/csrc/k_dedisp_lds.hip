@@ -16,9 +16,12 @@
 // Wavefronts split the tile: WD groups along DM (D trials each) x WT groups
 // along time (M chunks of 512 samples each). Lanes of a chunk read
 // consecutive 8-byte words, so LDS reads are free of bank conflicts.
-// Workgroups are ordered DM-tile-major and each XCD takes a contiguous run of
-// tiles, so the concurrently running tiles of one XCD are neighbours in time
-// whose input windows overlap in that XCD's L2.
+// Workgroups are ordered time-tile-major and each XCD takes a contiguous run of
+// tiles, so the concurrently running tiles of one XCD are neighbouring DM
+// tiles of the same time tile: for every channel their windows overlap by at
+// least the tile length, and the input one tile loads is mostly already in
+// that XCD's L2 (a DM-tile-major order re-reads the whole input from HBM once
+// per DM tile).
 #include "k_dedisp_lds.h"
 
 namespace sdd {
@@ -355,7 +358,7 @@ __device__ __forceinline__ void dd_tile(const LdsArgs& a, int32_t dtile, int32_t
     dd_tile_impl<D, M, WD, WT, CS, NLD, F, ES, false>(a, dtile, ttile, lds);
 }
 
-// Grid form: one workgroup per tile of one job, ordered DM-tile-major with a
+// Grid form: one workgroup per tile of one job, ordered time-tile-major with a
 // contiguous run of tiles per XCD (workgroups go to the 8 XCDs round-robin).
 template <int D, int M, int WD, int WT, int CS, int NLD, int F, int ES>
 __global__ __launch_bounds__(64 * WD * WT) void k_dedisp_lds(LdsArgs a) {
@@ -364,39 +367,33 @@ __global__ __launch_bounds__(64 * WD * WT) void k_dedisp_lds(LdsArgs a) {
   const int32_t b = blockIdx.x;
   const int32_t full = nblk & ~7;
   const int32_t L = b < full ? (b & 7) * (full >> 3) + (b >> 3) : b;
-  const int32_t dtile = L / a.n_ttiles;
-  dd_tile<D, M, WD, WT, CS, NLD, F, ES>(a, dtile, L - dtile * a.n_ttiles, lds);
+  const int32_t ttile = L / a.n_dtiles;
+  dd_tile<D, M, WD, WT, CS, NLD, F, ES>(a, L - ttile * a.n_dtiles, ttile, lds);
 }
 
 // Persistent form for a batch of jobs (beams x DM ranges with the same tile
-// shape): the global tile list (job by job, DM-tile-major inside a job) is
-// cut into 8 contiguous parts, one per XCD; the workgroups of an XCD take
-// the tiles of its part in order from an atomic counter until it runs dry.
+// shape): the global tile list (job by job, time-tile-major inside a job) is
+// cut into 8 contiguous parts, one per XCD. The workgroups of an XCD walk its
+// part in rounds: in round r workgroup k of the XCD takes tile r * n + k, so
+// the tiles running together on an XCD stay neighbours (and share input in
+// its L2) as they do in the grid form, without a tail per job.
 template <int D, int M, int WD, int WT, int CS, int NLD, int F, int ES>
 __global__ __launch_bounds__(64 * WD * WT) void k_dedisp_lds_multi(MultiArgs m) {
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
-  __shared__ int32_t s_tile;
   const int32_t total = m.tile_base[m.njobs];
-  const int xcd = blockIdx.x & 7;
+  const int xcd = blockIdx.x & 7;                  // workgroups go to XCDs round-robin
+  const int32_t k = blockIdx.x >> 3;               // index among this XCD's workgroups
+  const int32_t n = (int32_t)(gridDim.x >> 3);     // workgroups per XCD (grid is a multiple of 8)
   const int32_t lo = (int32_t)(((int64_t)total * xcd) >> 3);
   const int32_t hi = (int32_t)(((int64_t)total * (xcd + 1)) >> 3);
-  for (;;) {
-    if (threadIdx.x == 0) s_tile = lo + (int32_t)atomicAdd(&m.counters[xcd], 1u);
-    __syncthreads();
-    const int32_t t = s_tile;
-    __syncthreads();
-    if (t >= hi) break;
-    int j = 0;
+  int j = 0;
+  for (int32_t t = lo + k; t < hi; t += n) {
     while (j + 1 < m.njobs && t >= m.tile_base[j + 1]) ++j;
-    const LdsArgs a = m.jobs[j];
+    const LdsArgs& a = m.jobs[j];
     const int32_t L = t - m.tile_base[j];
-    const int32_t dtile = L / a.n_ttiles;
-    dd_tile<D, M, WD, WT, CS, NLD, F, ES>(a, dtile, L - dtile * a.n_ttiles, lds);
+    const int32_t ttile = L / a.n_dtiles;
+    dd_tile<D, M, WD, WT, CS, NLD, F, ES>(a, L - ttile * a.n_dtiles, ttile, lds);
   }
-}
-
-__global__ void k_zero_counters(uint32_t* c) {
-  if (threadIdx.x < 8) c[threadIdx.x] = 0u;
 }
 
 template <int D, int M, int WD, int WT, int CS, int NLD, int F, int ES>
@@ -418,7 +415,6 @@ hipError_t launch_multi(const MultiArgs& m, int32_t max_win, hipStream_t s) {
     return e;
   int nblk = (per_cu < 1 ? 1 : per_cu) * ncu;
   nblk = (nblk + 7) / 8 * 8;
-  hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, s, m.counters);
   hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(NT), lds, s, m);
   return hipGetLastError();
 }

@@ -219,12 +219,10 @@ sdd_status check_planes(const sdd_plan* p, const CallGeom& cg, const void* const
                         const int64_t* pitch);
 // Dedispersion of a set of jobs: jobs sharing an LDS tile shape go through the
 // persistent multi-job kernel; the rest are launched one by one.
-sdd_status launch_jobs_persistent(const std::vector<DedispArgs>& jobs, uint32_t* counters,
-                                  hipStream_t s);
+sdd_status launch_jobs_persistent(const std::vector<DedispArgs>& jobs, hipStream_t s);
 
 // ---- batches (batch.cpp) ------------------------------------------------
 
-constexpr int64_t kCounterBytes = 256;  // per-XCD tile counters at the workspace start
 
 // One chunk of a batch; ring_rows > 0 marks a time-major ring input whose
 // window starts at row ring_start.

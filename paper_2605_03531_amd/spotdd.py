@@ -369,7 +369,7 @@ class Server:
 
     def __init__(self, hbm_budget: int, device: int = 0, max_beams: int = 256,
                  nstreams: int = 2, max_batch: int = 8, ring_chunks: int = 2, cap: int = 1024,
-                 per_item: bool = False, fake_exec_us: Optional[int] = None):
+                 per_item: bool = True, fake_exec_us: Optional[int] = None):
         d = A.ServerDesc()
         d.hbm_budget = int(hbm_budget)
         d.device = int(device)
