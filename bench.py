@@ -77,6 +77,54 @@ def cpu_baseline(w, plan_delays, rows: int):
                       f"({os.cpu_count()} logical CPUs)"}
 
 
+# Candidate sifting measured after the step: stencils of (1, 4) DM steps x (16, 128) samples,
+# then clustering with a (10 DM steps, 512 samples) neighbourhood and 2 points per core.
+SIFT_STENCILS_STEPS = [(1.0, 16), (4.0, 128)]
+SIFT_EPS_STEPS = (10.0, 512)
+SIFT_MIN_PTS = 2
+
+
+def sift_bench(sdd, torch, plan, out, dm_step: float, large: int):
+    """Time sdd_sift_candidates (HIP events on its stream) on the step's own
+    candidate list and on a seeded list of `large` candidates."""
+    import ctypes as C
+    import synth
+    from paper_2605_03531_amd import _capi as A
+    L = A.lib()
+    st = [(a * dm_step, b) for a, b in SIFT_STENCILS_STEPS]
+    eps = (SIFT_EPS_STEPS[0] * dm_step, SIFT_EPS_STEPS[1])
+
+    def timed(o, reps):
+        plan.sift(o, stencils=st, eps=eps, min_pts=SIFT_MIN_PTS)  # warm-up, workspace sizing
+        torch.cuda.synchronize()
+        A.check(L.sdd_profile_enable(1), "profile")
+        for _ in range(reps):
+            res = plan.sift(o, stencils=st, eps=eps, min_pts=SIFT_MIN_PTS)
+        torch.cuda.synchronize()
+        ms, n = C.c_double(), C.c_int64()
+        A.check(L.sdd_profile_read(A.STAGES["sift"], C.byref(ms), C.byref(n)), "profile_read")
+        L.sdd_profile_enable(0)
+        kept, _ = res.host()
+        return ms.value / max(n.value, 1), len(kept)
+
+    n_step = min(int(out.ncand.cpu()[0]), out.cands.numel() // sdd.CAND_DTYPE.itemsize)
+    ms_step, kept_step = timed(out, 5)
+    ndm = plan.ndm_total
+    rng, dmi, smp, wid, snr = synth.candidate_list(21, [ndm], [1 << 18], n_events=large // 40,
+                                                   per_event=40, n_noise=large // 4)
+    rng, dmi, smp, wid, snr = rng[:large], dmi[:large], smp[:large], wid[:large], snr[:large]
+    arr = np.zeros(large, dtype=sdd.CAND_DTYPE)
+    m = len(rng)
+    arr["range"][:m], arr["dm_index"][:m], arr["sample"][:m] = rng, dmi, smp
+    arr["width"][:m], arr["snr"][:m] = wid, snr
+    big = sdd.SearchOut(None, None, torch.from_numpy(arr.view(np.uint8).copy()).to("cuda:0"),
+                        torch.tensor([m], dtype=torch.int32, device="cuda:0"))
+    ms_big, kept_big = timed(big, 3)
+    return {"stencils": [list(x) for x in st], "eps": list(eps), "min_pts": SIFT_MIN_PTS,
+            "step": {"candidates": n_step, "kept": kept_step, "ms": round(ms_step, 4)},
+            "seeded_list": {"candidates": m, "kept": kept_big, "ms": round(ms_big, 4)}}
+
+
 def serve_bench(sdd, torch, nbeams: int, sat_chunks: int, rt_periods: int, max_batch: int,
                 nstreams: int, per_item: bool = True):
     """Streaming server with nbeams beams (1024/2048/4096 channels by beam
@@ -284,6 +332,8 @@ def main() -> int:
     import ctypes as C
     stage = {}
     for name, sid in A.STAGES.items():
+        if name == "sift":  # not part of the step; measured separately below
+            continue
         ms, n = C.c_double(), C.c_int64()
         A.check(L.sdd_profile_read(sid, C.byref(ms), C.byref(n)), "profile_read")
         stage[name] = (ms.value / n.value if n.value else 0.0, n.value)
@@ -315,6 +365,8 @@ def main() -> int:
                                  if list(plan.get_tile(0)) == MEASURED_TRAFFIC["tile"] else None)},
         "cpu_baseline": None,
     }
+    res["sift"] = sift_bench(sdd, torch, plan, out, float(w.dm_list[1] - w.dm_list[0]), 1 << 16)
+    log(f"sift: {res['sift']}")
     if args.copy_calibration:
         src = torch.empty(1 << 30, dtype=torch.uint8, device=dev).fill_(7)
         dst = torch.empty_like(src)

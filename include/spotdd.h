@@ -374,11 +374,57 @@ sdd_status sdd_stream_poll(sdd_server* server, sdd_result* out, int32_t max, int
 sdd_status sdd_result_release(sdd_server* server, sdd_result* result);
 sdd_status sdd_server_query(sdd_server* server, sdd_server_stats* out);
 
+/* ---- candidate sifting (after the search) -------------------------------- */
+
+/* Removal of redundant candidates of one event with square stencils in the
+ * DM-time plane, then density-based (DBSCAN) clustering of the survivors in
+ * the DM-time plane, each cluster keeping its highest-S/N member (Section 2.1
+ * names both steps; Ester et al. 1996 for DBSCAN). Coordinates of a
+ * candidate: its FP64 trial DM from the plan and its window start in native
+ * samples (sample * decimation of its range). Candidate q is better than p
+ * when its float32 S/N is higher, or equal and q comes earlier in the list.
+ *   stencil k (0 <= k < nstencils), half-sizes (stencil_dm[k] pc cm^-3,
+ *     stencil_t[k] native samples): a candidate survives the pass when no
+ *     better candidate of the pass's input has |dDM| <= stencil_dm[k] and
+ *     |dt| <= stencil_t[k]; passes run in order on the previous survivors.
+ *   clustering (min_pts >= 1): neighbourhood |dDM| <= eps_dm and
+ *     |dt| <= eps_t, a point counting itself; core points have >= min_pts
+ *     neighbours; clusters are connected components of core points; a
+ *     non-core point with core neighbours joins the cluster of the earliest
+ *     one, otherwise it is noise and is dropped. min_pts == 0: no clustering,
+ *     every stencil survivor is kept with cluster size 1. */
+#define SDD_MAX_STENCILS 8
+typedef struct sdd_sift_desc {
+  int32_t nstencils;
+  int32_t min_pts;
+  double stencil_dm[SDD_MAX_STENCILS];
+  int64_t stencil_t[SDD_MAX_STENCILS];
+  double eps_dm;
+  int64_t eps_t;
+} sdd_sift_desc;
+
+/* Device scratch for sdd_sift_candidates on lists of up to cap candidates. */
+sdd_status sdd_sift_workspace_size(int32_t cap, int64_t* bytes);
+/* Sifts the candidate list of one sdd_search_boxcar / sdd_dedisperse_search
+ * call of the same plan: d_cands [cap] in (range, dm, sample) order and
+ * d_ncand, that call's device count (entries past cap are ignored). Writes
+ * the kept candidates (entries naming no trial of the plan are dropped) to
+ * d_out [cap] in list order, their number to
+ * *d_nout (device), and, if d_sizes is not NULL, each kept candidate's
+ * cluster size to d_sizes [cap] (device). Enqueued on stream; nothing is
+ * read back to the host. EINVAL on null buffers, cap < 1, nstencils outside
+ * 0..SDD_MAX_STENCILS, negative half-sizes or min_pts < 0; ENOMEM when
+ * ws_bytes is too small. */
+sdd_status sdd_sift_candidates(const sdd_plan* plan, const sdd_candidate* d_cands,
+                               const int32_t* d_ncand, int32_t cap, const sdd_sift_desc* desc,
+                               sdd_candidate* d_out, int32_t* d_nout, int32_t* d_sizes,
+                               void* d_workspace, int64_t ws_bytes, void* stream);
+
 /* ---- kernel timing (benchmarks) ----------------------------------------- */
 
 /* Stages whose kernels can be timed. */
 enum { SDD_STAGE_CORNER_TURN = 0, SDD_STAGE_DECIMATE = 1, SDD_STAGE_DEDISPERSE = 2,
-       SDD_STAGE_SEARCH = 3, SDD_NSTAGES = 4 };
+       SDD_STAGE_SEARCH = 3, SDD_STAGE_SIFT = 4, SDD_NSTAGES = 5 };
 
 /* on != 0: from now on every stage launch is bracketed by two HIP events
  * recorded on the launch stream; the accumulated times are reset. on == 0:

@@ -15,6 +15,7 @@ HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))
 SDD_MAX_RANGES = 16
 SDD_MAX_WIDTHS = 32
 SDD_MAX_WMAX = 8192
+SDD_MAX_STENCILS = 8
 SDD_CHAN_MAJOR, SDD_TIME_MAJOR = 0, 1
 
 STATUS = {0: "SDD_OK", -1: "SDD_EINVAL", -2: "SDD_ERANGE", -3: "SDD_ENOMEM",
@@ -97,6 +98,10 @@ class ServerStats(C.Structure):
     _fields_ = [("open_streams", i32), ("queued_results", i32), ("hbm_used", i64),
                 ("batches", i64), ("chunks", i64), ("busy_ms", f64)]
 
+class SiftDesc(C.Structure):
+    _fields_ = [("nstencils", i32), ("min_pts", i32), ("stencil_dm", f64 * SDD_MAX_STENCILS),
+                ("stencil_t", i64 * SDD_MAX_STENCILS), ("eps_dm", f64), ("eps_t", i64)]
+
 PlanP = vp
 
 _PROTOS = {
@@ -130,10 +135,13 @@ _PROTOS = {
     "sdd_stream_poll": (i32, [vp, C.POINTER(Result), i32, i32, C.POINTER(i32)]),
     "sdd_result_release": (i32, [vp, C.POINTER(Result)]),
     "sdd_server_query": (i32, [vp, C.POINTER(ServerStats)]),
+    "sdd_sift_workspace_size": (i32, [i32, C.POINTER(i64)]),
+    "sdd_sift_candidates": (i32, [vp, vp, vp, i32, C.POINTER(SiftDesc), vp, vp, vp, vp, i64,
+                                  vp]),
     "sdd_profile_enable": (i32, [i32]),
     "sdd_profile_read": (i32, [i32, C.POINTER(f64), C.POINTER(i64)]),
 }
-STAGES = {"corner_turn": 0, "decimate": 1, "dedisperse": 2, "search": 3}
+STAGES = {"corner_turn": 0, "decimate": 1, "dedisperse": 2, "search": 3, "sift": 4}
 
 _lib = None
 

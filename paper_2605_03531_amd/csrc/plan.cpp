@@ -232,6 +232,13 @@ sdd_status plan_upload(const sdd_plan* p) {
     p->d_delays[r] = d;
     SDD_HIP_TRY(hipMemcpy(d, cm.data(), cm.size() * sizeof(int32_t), hipMemcpyHostToDevice));
   }
+  {
+    std::vector<double> all;
+    for (const Range& R : p->ranges) all.insert(all.end(), R.dms.begin(), R.dms.end());
+    SDD_HIP_TRY(hipMalloc(&p->d_dms, all.size() * sizeof(double)));
+    SDD_HIP_TRY(hipMemcpy(p->d_dms, all.data(), all.size() * sizeof(double),
+                          hipMemcpyHostToDevice));
+  }
   if (!p->widths.empty()) {
     SDD_HIP_TRY(hipMalloc(&p->d_widths, p->widths.size() * sizeof(int32_t)));
     SDD_HIP_TRY(hipMemcpy(p->d_widths, p->widths.data(), p->widths.size() * sizeof(int32_t),
@@ -366,6 +373,7 @@ extern "C" sdd_status sdd_plan_destroy(sdd_plan* p) {
     (void)hipSetDevice(p->uploaded_device);
     for (int32_t* d : p->d_delays) (void)hipFree(d);
     if (p->d_widths) (void)hipFree(p->d_widths);
+    if (p->d_dms) (void)hipFree(p->d_dms);
     (void)hipSetDevice(prev);
   }
   delete p;

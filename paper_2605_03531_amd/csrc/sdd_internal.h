@@ -112,6 +112,7 @@ struct sdd_plan {
   // per range, [round_up(nchan, kDelayRowPad)][ndm_r]; rows past nchan are 0
   mutable std::vector<int32_t*> d_delays;
   mutable int32_t* d_widths = nullptr;
+  mutable double* d_dms = nullptr;  // every trial DM, ranges in order (global trial index)
 
   int32_t cells_for(int64_t n_owned_r) const {
     return widths.empty() ? 0 : (int32_t)((n_owned_r + cand_block - 1) / cand_block);

@@ -269,6 +269,54 @@ class Plan:
                 "sdd_dedisperse_search")
         return planes, out
 
+    def sift(self, out: SearchOut, stencils=(), eps=None, min_pts: int = 0, result=None,
+             workspace=None, stream=None) -> "SiftOut":
+        """Candidate sifting of a search result of this plan (sdd_sift_candidates):
+        stencils = [(half-size in DM, half-size in native samples), ...] applied
+        in order; eps = (DM, samples) neighbourhood and min_pts the core
+        threshold of the clustering (0 = no clustering)."""
+        import torch
+        cap = out.cands.numel() // CAND_DTYPE.itemsize
+        d = A.SiftDesc()
+        if len(stencils) > A.SDD_MAX_STENCILS:
+            raise ValueError(f"at most {A.SDD_MAX_STENCILS} stencils")
+        d.nstencils = len(stencils)
+        for k, (sd, st) in enumerate(stencils):
+            d.stencil_dm[k] = float(sd)
+            d.stencil_t[k] = int(st)
+        d.min_pts = int(min_pts)
+        if eps is not None:
+            d.eps_dm, d.eps_t = float(eps[0]), int(eps[1])
+        dev = out.cands.device
+        if result is None:
+            result = SiftOut(torch.empty(cap * CAND_DTYPE.itemsize, dtype=torch.uint8, device=dev),
+                             torch.zeros(1, dtype=torch.int32, device=dev),
+                             torch.empty(cap, dtype=torch.int32, device=dev))
+        if workspace is None:
+            nb = C.c_int64()
+            A.check(A.lib().sdd_sift_workspace_size(cap, C.byref(nb)), "sdd_sift_workspace_size")
+            workspace = torch.empty(nb.value, dtype=torch.uint8, device=dev)
+        A.check(A.lib().sdd_sift_candidates(self._p, out.cands.data_ptr(), out.ncand.data_ptr(),
+                                            cap, C.byref(d), result.cands.data_ptr(),
+                                            result.n.data_ptr(), result.sizes.data_ptr(),
+                                            workspace.data_ptr(), workspace.numel(),
+                                            _stream_handle(stream, self.device)),
+                "sdd_sift_candidates")
+        return result
+
+
+@dataclass
+class SiftOut:
+    cands: "object"    # device uint8 tensor holding sdd_candidate[cap]
+    n: "object"        # device int32 tensor [1]
+    sizes: "object"    # device int32 tensor [cap]
+
+    def host(self):
+        """(kept candidates as a structured array, their cluster sizes)."""
+        n = int(self.n.cpu()[0])
+        raw = self.cands[: n * CAND_DTYPE.itemsize].cpu().numpy().tobytes()
+        return np.frombuffer(raw, dtype=CAND_DTYPE), self.sizes[:n].cpu().numpy()
+
 
 def plane_host(plane, cols: int) -> np.ndarray:
     """Device int32 plane -> host uint32 [ndm][cols] (the defined columns)."""

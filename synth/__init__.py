@@ -27,6 +27,7 @@ from typing import Callable, List, Optional, Sequence, Tuple
 import numpy as np
 
 __all__ = [
+    "candidate_list",
     "normal_u8_table", "filterbank", "inject_pulse", "to_time_major",
     "Pulse", "Workload", "tiny", "full_band", "multi_range", "batched_beams",
     "stream_beam_params",
@@ -235,3 +236,45 @@ def stream_beam_params(nbeams: int = 160):
     """Channel count per beam for the streaming workload: beam b gets
     [1024, 2048, 4096][b % 3] channels over 750 -> 550 MHz."""
     return [[1024, 2048, 4096][b % 3] for b in range(nbeams)]
+
+
+def candidate_list(seed: int, ndm: Sequence[int], n_owned: Sequence[int], n_events: int = 40,
+                   per_event: int = 30, n_noise: int = 200, max_width: int = 64):
+    """Seeded candidate lists in the search's output order (range, DM index,
+    sample) for testing candidate sifting: events (clumps of candidates
+    spread over a few trials and samples around a centre, S/N falling away
+    from it, quantised to 1/8 so that ties occur) plus scattered weak
+    candidates. Returns (range, dm_index, sample, width, snr float32)
+    arrays. ndm / n_owned give each range's trial count and owned samples."""
+    g = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 77])))
+    nr = len(ndm)
+    rows = []
+    for _ in range(n_events):
+        r = int(g.integers(0, nr))
+        ci = int(g.integers(0, ndm[r]))
+        cs = int(g.integers(0, n_owned[r]))
+        peak = float(g.uniform(8.0, 40.0))
+        for _ in range(per_event):
+            di = int(round(g.normal(0.0, 3.0)))
+            ds = int(round(g.normal(0.0, 40.0)))
+            i, s = ci + di, cs + ds
+            if 0 <= i < ndm[r] and 0 <= s < n_owned[r]:
+                snr = peak - 0.4 * abs(di) - 0.02 * abs(ds) - float(g.exponential(0.5))
+                rows.append((r, i, s, int(g.integers(1, max_width + 1)), max(snr, 6.0)))
+    for _ in range(n_noise):
+        r = int(g.integers(0, nr))
+        rows.append((r, int(g.integers(0, ndm[r])), int(g.integers(0, n_owned[r])),
+                     int(g.integers(1, max_width + 1)), float(g.uniform(6.0, 9.0))))
+    # one candidate per (range, trial, sample), as the search reports at most one
+    # per cell; quantised S/N makes ties frequent
+    uniq = {}
+    for r, i, s, w, snr in rows:
+        uniq[(r, i, s)] = (w, np.float32(round(snr * 8.0) / 8.0))
+    keys = sorted(uniq)
+    rng_ = np.array([k[0] for k in keys], dtype=np.int32)
+    dmi = np.array([k[1] for k in keys], dtype=np.int32)
+    smp = np.array([k[2] for k in keys], dtype=np.int64)
+    wid = np.array([uniq[k][0] for k in keys], dtype=np.int32)
+    snr = np.array([uniq[k][1] for k in keys], dtype=np.float32)
+    return rng_, dmi, smp, wid, snr
+

@@ -175,3 +175,30 @@ def test_unsorted_dm_list_uses_the_direct_kernel():
             p.set_tile(t)
     q = sdd.Plan([500.0, 400.0, 300.0], 1e-3, dm_list=[0.0, 3.0, 5.0])
     assert q.get_tile(0)[0] >= 1
+
+
+def test_sift_validates_before_touching_the_device():
+    L = A.lib()
+    nb = C.c_int64()
+    assert L.sdd_sift_workspace_size(0, C.byref(nb)) == A.SDD_EINVAL
+    assert L.sdd_sift_workspace_size(1000, C.byref(nb)) == A.SDD_OK and nb.value > 1000 * 40
+    p = sdd.Plan([500.0, 300.0], 1e-3, dm_list=[0.0, 5.0], widths=[1])
+    d = A.SiftDesc()
+    args = lambda desc, cap=16, ws=1 << 20: (p.handle, 1, 1, cap, C.byref(desc), 1, 1, None, 1,
+                                           ws, None)
+    assert L.sdd_sift_candidates(None, 1, 1, 16, C.byref(d), 1, 1, None, 1, 1 << 20,
+                                 None) == A.SDD_EINVAL
+    assert L.sdd_sift_candidates(*args(d, cap=0)) == A.SDD_EINVAL
+    d.nstencils = A.SDD_MAX_STENCILS + 1
+    assert L.sdd_sift_candidates(*args(d)) == A.SDD_EINVAL
+    d.nstencils = 1
+    d.stencil_dm[0] = -1.0
+    assert L.sdd_sift_candidates(*args(d)) == A.SDD_EINVAL
+    d.stencil_dm[0] = 1.0
+    d.min_pts = -2
+    assert L.sdd_sift_candidates(*args(d)) == A.SDD_EINVAL
+    d.min_pts = 2
+    d.eps_t = -1
+    assert L.sdd_sift_candidates(*args(d)) == A.SDD_EINVAL
+    d.eps_t = 10
+    assert L.sdd_sift_candidates(*args(d, ws=16)) == A.SDD_ENOMEM
