@@ -374,6 +374,54 @@ sdd_status sdd_stream_poll(sdd_server* server, sdd_result* out, int32_t max, int
 sdd_status sdd_result_release(sdd_server* server, sdd_result* result);
 sdd_status sdd_server_query(sdd_server* server, sdd_server_stats* out);
 
+/* ---- RFI pre-conditioning (before dedispersion) --------------------------- */
+
+/* Bandpass correction with time- and frequency-domain flagging of one chunk
+ * (Section 2.1 and the paper's figure of its RFI tool), as exact integer
+ * maps applied while the chunk is staged for dedispersion:
+ *   m_c   mean of channel c over the unflagged samples (all in round 1), FP64
+ *         of the exact integer sum;
+ *   b_c   lower median of m over the median_window channels centred on c
+ *         (clipped to the band): the bandpass;
+ *   channel c flagged when |r_c - median(r)| > chan_sigma * 1.4826 * MAD(r),
+ *         r = m - b (lower medians; a zero MAD flags nothing);
+ *   z_t   sum of x[c][t] over unflagged channels; sample t flagged when
+ *         |z_t - median(z)| > time_sigma * 1.4826 * MAD(z);
+ *   repeated `rounds` times, each round from the previous round's flags.
+ * Output: lut [nchan][256] with lut[c][v] = 0 for a flagged channel, else
+ * clip(v - floor(b_c + 0.5) + floor(median(b) + 0.5), 0, 255); time mask
+ * [nsamp_in], 1 = keep; optionally the channel flags [nchan]. */
+typedef struct sdd_rfi_desc {
+  int32_t median_window;  /* odd, 1..63 (21) */
+  int32_t rounds;         /* 1..16 (2) */
+  double chan_sigma;      /* (4.0) */
+  double time_sigma;      /* (3.0) */
+} sdd_rfi_desc;
+
+/* Device scratch for sdd_rfi_estimate on chunks of nsamp_in samples. */
+sdd_status sdd_rfi_workspace_size(const sdd_plan* plan, int64_t nsamp_in, int64_t* bytes);
+/* Estimates the maps from one chunk in the plan's layout (d_in, in_pitch as
+ * for sdd_dedisperse). d_chan_flags may be NULL. Enqueued on stream. */
+sdd_status sdd_rfi_estimate(const sdd_plan* plan, const uint8_t* d_in, int64_t nsamp_in,
+                            int64_t in_pitch, const sdd_rfi_desc* desc, uint8_t* d_lut,
+                            uint8_t* d_time_mask, int32_t* d_chan_flags, void* d_workspace,
+                            int64_t ws_bytes, void* stream);
+/* Workspace bytes of sdd_dedisperse_search_pre (lib_planes != 0: planes kept
+ * in the workspace, as d_planes == NULL). */
+sdd_status sdd_pre_workspace_size(const sdd_plan* plan, int64_t nsamp_in, int32_t lib_planes,
+                                  int64_t* bytes);
+/* sdd_dedisperse_search of the pre-conditioned chunk
+ * x'[c][t] = (d_time_mask == NULL || d_time_mask[t]) ? lut[c][x[c][t]] : 0,
+ * with d_lut == NULL meaning the identity map. The maps are applied in the
+ * corner turn (time-major input) or in a row copy (channel-major input). */
+sdd_status sdd_dedisperse_search_pre(const sdd_plan* plan, const uint8_t* d_in, int64_t nsamp_in,
+                                     int64_t in_pitch, const uint8_t* d_lut,
+                                     const uint8_t* d_time_mask, uint32_t* const* d_planes,
+                                     const int64_t* plane_pitch, sdd_dm_best* d_best,
+                                     sdd_dm_stats* d_stats, sdd_candidate* d_cands, int32_t cap,
+                                     int32_t* d_ncand, void* d_workspace, int64_t ws_bytes,
+                                     void* stream);
+
 /* ---- candidate sifting (after the search) -------------------------------- */
 
 /* Removal of redundant candidates of one event with square stencils in the

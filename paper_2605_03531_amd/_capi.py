@@ -98,6 +98,11 @@ class ServerStats(C.Structure):
     _fields_ = [("open_streams", i32), ("queued_results", i32), ("hbm_used", i64),
                 ("batches", i64), ("chunks", i64), ("busy_ms", f64)]
 
+class RfiDesc(C.Structure):
+    _fields_ = [("median_window", i32), ("rounds", i32), ("chan_sigma", f64),
+                ("time_sigma", f64)]
+
+
 class SiftDesc(C.Structure):
     _fields_ = [("nstencils", i32), ("min_pts", i32), ("stencil_dm", f64 * SDD_MAX_STENCILS),
                 ("stencil_t", i64 * SDD_MAX_STENCILS), ("eps_dm", f64), ("eps_t", i64)]
@@ -135,6 +140,11 @@ _PROTOS = {
     "sdd_stream_poll": (i32, [vp, C.POINTER(Result), i32, i32, C.POINTER(i32)]),
     "sdd_result_release": (i32, [vp, C.POINTER(Result)]),
     "sdd_server_query": (i32, [vp, C.POINTER(ServerStats)]),
+    "sdd_rfi_workspace_size": (i32, [vp, i64, C.POINTER(i64)]),
+    "sdd_rfi_estimate": (i32, [vp, vp, i64, i64, C.POINTER(RfiDesc), vp, vp, vp, vp, i64, vp]),
+    "sdd_pre_workspace_size": (i32, [vp, i64, i32, C.POINTER(i64)]),
+    "sdd_dedisperse_search_pre": (i32, [vp, vp, i64, i64, vp, vp, C.POINTER(vp), C.POINTER(i64),
+                                        vp, vp, vp, i32, vp, vp, i64, vp]),
     "sdd_sift_workspace_size": (i32, [i32, C.POINTER(i64)]),
     "sdd_sift_candidates": (i32, [vp, vp, vp, i32, C.POINTER(SiftDesc), vp, vp, vp, vp, i64,
                                   vp]),

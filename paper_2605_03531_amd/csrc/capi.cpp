@@ -35,7 +35,7 @@ sdd_status check_input(const sdd_plan* p, const uint8_t* d_in, int64_t nsamp_in,
 sdd_status prep_item(const sdd_plan* p, const CallGeom& cg, const uint8_t* d_in, int64_t nsamp_in,
                      int64_t in_pitch, uint32_t* const* planes, const int64_t* pitch, uint8_t* ws,
                      hipStream_t s, std::vector<DedispArgs>* jobs, int64_t ring_rows,
-                     int64_t ring_start) {
+                     int64_t ring_start, const Precond* pre) {
   const WsLayout& L = cg.ws;
   const uint8_t* src = d_in;
   int64_t src_pitch = in_pitch;
@@ -43,9 +43,16 @@ sdd_status prep_item(const sdd_plan* p, const CallGeom& cg, const uint8_t* d_in,
     uint8_t* ct = ws + L.ct_off;
     StageTimer tm(SDD_STAGE_CORNER_TURN, s);
     SDD_HIP_TRY(launch_corner_turn(d_in, nsamp_in, in_pitch, p->nchan, ct, L.ct_pitch, s,
-                                   ring_rows, ring_start));
+                                   ring_rows, ring_start, pre ? pre->lut : nullptr,
+                                   pre ? pre->tmask : nullptr));
     src = ct;
     src_pitch = L.ct_pitch;
+  } else if (pre && (pre->lut || pre->tmask)) {
+    StageTimer tm(SDD_STAGE_CORNER_TURN, s);
+    SDD_HIP_TRY(launch_precond_rows(d_in, in_pitch, nsamp_in, p->nchan, pre->lut, pre->tmask,
+                                    pre->rows, pre->rows_pitch, s));
+    src = pre->rows;
+    src_pitch = pre->rows_pitch;
   }
   // each decimation is built from the largest smaller one that divides it
   std::vector<uint16_t*> dbuf(L.decs.size());
@@ -101,9 +108,10 @@ sdd_status prep_item(const sdd_plan* p, const CallGeom& cg, const uint8_t* d_in,
 
 sdd_status run_dedisperse(const sdd_plan* p, const CallGeom& cg, const uint8_t* d_in,
                           int64_t nsamp_in, int64_t in_pitch, uint32_t* const* planes,
-                          const int64_t* pitch, uint8_t* ws, hipStream_t s) {
+                          const int64_t* pitch, uint8_t* ws, hipStream_t s, const Precond* pre) {
   std::vector<DedispArgs> jobs;
-  sdd_status st = prep_item(p, cg, d_in, nsamp_in, in_pitch, planes, pitch, ws, s, &jobs);
+  sdd_status st = prep_item(p, cg, d_in, nsamp_in, in_pitch, planes, pitch, ws, s, &jobs, 0, 0,
+                            pre);
   if (st != SDD_OK) return st;
   for (const auto& a : jobs) {
     StageTimer tm(SDD_STAGE_DEDISPERSE, s);

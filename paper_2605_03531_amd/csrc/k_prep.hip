@@ -20,7 +20,9 @@ __global__ __launch_bounds__(256) void k_corner_turn(const uint8_t* __restrict__
                                                      int64_t in_pitch, int32_t nchan,
                                                      uint8_t* __restrict__ out, int64_t out_pitch,
                                                      int dword_in, int dword_out,
-                                                     int64_t ring_rows, int64_t ring_start) {
+                                                     int64_t ring_rows, int64_t ring_start,
+                                                     const uint8_t* __restrict__ lut,
+                                                     const uint8_t* __restrict__ tmask) {
   __shared__ __attribute__((aligned(16))) uint8_t tile[kCtChan][kCtTime + kCtPad];
   const int tid = threadIdx.x;
   const int32_t c0 = blockIdx.y * kCtChan;
@@ -59,10 +61,44 @@ __global__ __launch_bounds__(256) void k_corner_turn(const uint8_t* __restrict__
     const int64_t t = t0 + tt;
     if (c >= nchan || t >= nsamp) continue;
     uint8_t* dst = out + (int64_t)c * out_pitch + t;
+    uint32_t v = *reinterpret_cast<const uint32_t*>(&tile[cr][tt]);
+    if (lut || tmask) {
+      // pre-conditioning: per-channel byte map, then the time mask
+      uint32_t w = 0;
+      for (int b = 0; b < 4; ++b) {
+        uint32_t x = (v >> (8 * b)) & 255u;
+        if (lut) x = lut[(int64_t)c * 256 + x];
+        if (tmask && (t + b >= nsamp || !tmask[t + b])) x = 0;
+        w |= x << (8 * b);
+      }
+      v = w;
+    }
     if (dword_out && t + 3 < nsamp) {
-      *reinterpret_cast<uint32_t*>(dst) = *reinterpret_cast<const uint32_t*>(&tile[cr][tt]);
+      *reinterpret_cast<uint32_t*>(dst) = v;
     } else {
-      for (int b = 0; b < 4 && t + b < nsamp; ++b) dst[b] = tile[cr][tt + b];
+      for (int b = 0; b < 4 && t + b < nsamp; ++b) dst[b] = (uint8_t)(v >> (8 * b));
+    }
+  }
+}
+
+// Channel rows through the pre-conditioning maps: 4 samples per thread.
+__global__ __launch_bounds__(256) void k_precond_rows(const uint8_t* __restrict__ in,
+                                                      int64_t in_pitch, int64_t nsamp,
+                                                      int32_t nchan,
+                                                      const uint8_t* __restrict__ lut,
+                                                      const uint8_t* __restrict__ tmask,
+                                                      uint8_t* __restrict__ out,
+                                                      int64_t out_pitch) {
+  const int64_t t = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+  if (t >= nsamp) return;
+  for (int32_t c = blockIdx.y; c < nchan; c += gridDim.y) {
+    const uint8_t* src = in + (int64_t)c * in_pitch;
+    uint8_t* dst = out + (int64_t)c * out_pitch;
+    for (int b = 0; b < 4 && t + b < nsamp; ++b) {
+      uint32_t x = src[t + b];
+      if (lut) x = lut[(int64_t)c * 256 + x];
+      if (tmask && !tmask[t + b]) x = 0;
+      dst[t + b] = (uint8_t)x;
     }
   }
 }
@@ -86,12 +122,21 @@ __global__ __launch_bounds__(256) void k_decimate(const Tin* __restrict__ in, in
 
 hipError_t launch_corner_turn(const uint8_t* in, int64_t nsamp, int64_t in_pitch, int32_t nchan,
                               uint8_t* out, int64_t out_pitch, hipStream_t s, int64_t ring_rows,
-                              int64_t ring_start) {
+                              int64_t ring_start, const uint8_t* lut, const uint8_t* tmask) {
   const int dword_in = ((uintptr_t)in % 4 == 0) && (in_pitch % 4 == 0);
   const int dword_out = ((uintptr_t)out % 4 == 0) && (out_pitch % 4 == 0);
   dim3 grid((unsigned)((nsamp + kCtTime - 1) / kCtTime), (unsigned)((nchan + kCtChan - 1) / kCtChan));
   hipLaunchKernelGGL(k_corner_turn, grid, dim3(256), 0, s, in, nsamp, in_pitch, nchan, out,
-                     out_pitch, dword_in, dword_out, ring_rows, ring_start);
+                     out_pitch, dword_in, dword_out, ring_rows, ring_start, lut, tmask);
+  return hipGetLastError();
+}
+
+hipError_t launch_precond_rows(const uint8_t* in, int64_t in_pitch, int64_t nsamp, int32_t nchan,
+                               const uint8_t* lut, const uint8_t* tmask, uint8_t* out,
+                               int64_t out_pitch, hipStream_t s) {
+  dim3 grid((unsigned)((nsamp + 1023) / 1024), (unsigned)(nchan < 65535 ? nchan : 65535));
+  hipLaunchKernelGGL(k_precond_rows, grid, dim3(256), 0, s, in, in_pitch, nsamp, nchan, lut, tmask,
+                     out, out_pitch);
   return hipGetLastError();
 }
 

@@ -143,9 +143,17 @@ inline int32_t lds_window_bytes(int32_t tt, int32_t span, int es) {
 
 // ring_rows > 0: `in` is a ring of ring_rows spectra and the window starts at
 // row ring_start (rows wrap modulo ring_rows).
+// lut (optional, [nchan][256]) maps every byte of channel c through
+// lut[c][v]; tmask (optional, [nsamp]) zeroes window sample t where tmask[t]
+// is 0 (RFI pre-conditioning).
 hipError_t launch_corner_turn(const uint8_t* in, int64_t nsamp, int64_t in_pitch, int32_t nchan,
                               uint8_t* out, int64_t out_pitch, hipStream_t s,
-                              int64_t ring_rows = 0, int64_t ring_start = 0);
+                              int64_t ring_rows = 0, int64_t ring_start = 0,
+                              const uint8_t* lut = nullptr, const uint8_t* tmask = nullptr);
+// Channel rows copied through the same lut / tmask.
+hipError_t launch_precond_rows(const uint8_t* in, int64_t in_pitch, int64_t nsamp, int32_t nchan,
+                               const uint8_t* lut, const uint8_t* tmask, uint8_t* out,
+                               int64_t out_pitch, hipStream_t s);
 // out[c][j] = sum_{k<factor} in[c][j*factor+k], j < out_len; in is u8 or u16.
 hipError_t launch_decimate(const void* in, int in_bytes, int64_t in_pitch, int32_t nchan,
                            int32_t factor, uint16_t* out, int64_t out_pitch, int64_t out_len,
@@ -204,13 +212,23 @@ hipError_t launch_search(const SearchArgs& a, hipStream_t s);
 
 // Corner turn and decimations of one chunk; appends one dedispersion job per
 // DM range (not launched).
+// RFI pre-conditioning of a call's input: x'[c][t] = tmask[t] ? lut[c][x] : 0
+// (either map may be null). Channel-major input is copied through it into
+// rows [nchan][rows_pitch] (scratch past the call's workspace).
+struct Precond {
+  const uint8_t* lut = nullptr;
+  const uint8_t* tmask = nullptr;
+  uint8_t* rows = nullptr;
+  int64_t rows_pitch = 0;
+};
 sdd_status prep_item(const sdd_plan* p, const CallGeom& cg, const uint8_t* d_in, int64_t nsamp_in,
                      int64_t in_pitch, uint32_t* const* planes, const int64_t* pitch, uint8_t* ws,
                      hipStream_t s, std::vector<DedispArgs>* jobs, int64_t ring_rows = 0,
-                     int64_t ring_start = 0);
+                     int64_t ring_start = 0, const Precond* pre = nullptr);
 sdd_status run_dedisperse(const sdd_plan* p, const CallGeom& cg, const uint8_t* d_in,
                           int64_t nsamp_in, int64_t in_pitch, uint32_t* const* planes,
-                          const int64_t* pitch, uint8_t* ws, hipStream_t s);
+                          const int64_t* pitch, uint8_t* ws, hipStream_t s,
+                          const Precond* pre = nullptr);
 sdd_status run_search(const sdd_plan* p, const CallGeom& cg, const uint32_t* const* planes,
                       const int64_t* pitch, sdd_dm_best* best, sdd_dm_stats* stats,
                       sdd_candidate* cands, int32_t cap, int32_t* ncand, uint8_t* ws,

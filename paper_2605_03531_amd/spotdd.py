@@ -248,26 +248,66 @@ class Plan:
         return out
 
     def dedisperse_search(self, x, planes=None, out: Optional[SearchOut] = None,
-                          cap: int = 65536, workspace=None, stream=None):
+                          cap: int = 65536, workspace=None, stream=None, lut=None,
+                          time_mask=None):
         """Returns (planes or None, SearchOut). planes=None keeps the planes
-        inside the workspace (not returned)."""
+        inside the workspace (not returned). lut ([nchan][256] uint8) and
+        time_mask ([nsamp] uint8, 1 = keep) pre-condition the chunk first
+        (sdd_dedisperse_search_pre)."""
         nsamp, pitch = self._input(x)
+        pre = lut is not None or time_mask is not None
         if out is None:
             out = self.alloc_search_out(cap)
         if workspace is None:
-            workspace = self.workspace(nsamp, with_planes=planes is None)
+            if pre:
+                nb = C.c_int64()
+                A.check(A.lib().sdd_pre_workspace_size(self._p, nsamp, 1 if planes is None else 0,
+                                                       C.byref(nb)), "sdd_pre_workspace_size")
+                workspace = _torch().empty(max(nb.value, 1), dtype=_torch().uint8,
+                                           device=f"cuda:{self.device}")
+            else:
+                workspace = self.workspace(nsamp, with_planes=planes is None)
         if planes is None:
             ptrs, pp = None, None
         else:
             ptrs, pp = self._planes(planes)
         cap = out.cands.numel() // CAND_DTYPE.itemsize
-        A.check(A.lib().sdd_dedisperse_search(self._p, x.data_ptr(), nsamp, pitch, ptrs, pp,
-                                              out.best.data_ptr(), out.stats.data_ptr(),
-                                              out.cands.data_ptr(), cap, out.ncand.data_ptr(),
-                                              workspace.data_ptr(), workspace.numel(),
-                                              _stream_handle(stream, self.device)),
-                "sdd_dedisperse_search")
+        common = (out.best.data_ptr(), out.stats.data_ptr(), out.cands.data_ptr(), cap,
+                  out.ncand.data_ptr(), workspace.data_ptr(), workspace.numel(),
+                  _stream_handle(stream, self.device))
+        if pre:
+            A.check(A.lib().sdd_dedisperse_search_pre(
+                self._p, x.data_ptr(), nsamp, pitch,
+                None if lut is None else lut.data_ptr(),
+                None if time_mask is None else time_mask.data_ptr(), ptrs, pp, *common),
+                "sdd_dedisperse_search_pre")
+        else:
+            A.check(A.lib().sdd_dedisperse_search(self._p, x.data_ptr(), nsamp, pitch, ptrs, pp,
+                                                  *common), "sdd_dedisperse_search")
         return planes, out
+
+    def rfi_estimate(self, x, median_window: int = 21, rounds: int = 2,
+                     chan_sigma: float = 4.0, time_sigma: float = 3.0, stream=None):
+        """Bandpass and flags of one chunk in this plan's layout
+        (sdd_rfi_estimate). Returns device tensors (lut [nchan][256] uint8,
+        time mask [nsamp] uint8, channel flags [nchan] int32)."""
+        torch = _torch()
+        nsamp, pitch = self._input(x)
+        d = A.RfiDesc(int(median_window), int(rounds), float(chan_sigma), float(time_sigma))
+        nb = C.c_int64()
+        A.check(A.lib().sdd_rfi_workspace_size(self._p, nsamp, C.byref(nb)),
+                "sdd_rfi_workspace_size")
+        dev = f"cuda:{self.device}"
+        ws = torch.empty(nb.value, dtype=torch.uint8, device=dev)
+        lut = torch.empty((self.nchan, 256), dtype=torch.uint8, device=dev)
+        mask = torch.empty(nsamp, dtype=torch.uint8, device=dev)
+        flags = torch.empty(self.nchan, dtype=torch.int32, device=dev)
+        A.check(A.lib().sdd_rfi_estimate(self._p, x.data_ptr(), nsamp, pitch, C.byref(d),
+                                         lut.data_ptr(), mask.data_ptr(), flags.data_ptr(),
+                                         ws.data_ptr(), ws.numel(),
+                                         _stream_handle(stream, self.device)),
+                "sdd_rfi_estimate")
+        return lut, mask, flags
 
     def sift(self, out: SearchOut, stencils=(), eps=None, min_pts: int = 0, result=None,
              workspace=None, stream=None) -> "SiftOut":

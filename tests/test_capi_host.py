@@ -202,3 +202,27 @@ def test_sift_validates_before_touching_the_device():
     assert L.sdd_sift_candidates(*args(d)) == A.SDD_EINVAL
     d.eps_t = 10
     assert L.sdd_sift_candidates(*args(d, ws=16)) == A.SDD_ENOMEM
+
+
+def test_rfi_entry_points_validate_before_touching_the_device():
+    L = A.lib()
+    p = sdd.Plan([500.0, 400.0, 300.0], 1e-3, dm_list=[0.0, 5.0], widths=[1], layout="time")
+    nb = C.c_int64()
+    assert L.sdd_rfi_workspace_size(p.handle, 0, C.byref(nb)) == A.SDD_EINVAL
+    assert L.sdd_rfi_workspace_size(p.handle, 1000, C.byref(nb)) == A.SDD_OK
+    ws = nb.value
+    good = A.RfiDesc(21, 2, 4.0, 3.0)
+    call = lambda d, pitch=3, wsb=ws: L.sdd_rfi_estimate(p.handle, 1, 1000, pitch, C.byref(d), 1,
+                                                          1, None, 1, wsb, None)
+    for bad in (A.RfiDesc(20, 2, 4.0, 3.0), A.RfiDesc(65, 2, 4.0, 3.0),
+                A.RfiDesc(21, 0, 4.0, 3.0), A.RfiDesc(21, 2, 0.0, 3.0),
+                A.RfiDesc(21, 2, 4.0, -1.0)):
+        assert call(bad) == A.SDD_EINVAL
+    assert call(good, pitch=2) == A.SDD_EINVAL          # time-major pitch < nchan
+    assert call(good, wsb=ws - 1) == A.SDD_ENOMEM
+    # the pre-conditioned search checks its workspace like the plain one
+    T = p.overlap + 100
+    assert L.sdd_pre_workspace_size(p.handle, T, 1, C.byref(nb)) == A.SDD_OK
+    best = (C.c_byte * 64)()
+    assert L.sdd_dedisperse_search_pre(p.handle, 1, T, 3, None, None, None, None, best, None,
+                                       None, 0, best, 1, nb.value - 1, None) == A.SDD_ENOMEM
