@@ -20,6 +20,8 @@ It follows, in order:
   * Section 2.1, before dedispersion: RFI mitigation by bandpass correction
     and time- and frequency-domain flagging, as the figure of the paper's
     RFI tool describes it (oracle.rfi);
+  * Sections 2.1 and 3.3: robust noise statistics (sigma-clipped moments,
+    median and MAD) for the S/N of the search (oracle.robust);
   * Section 2.1, after the search: removal of redundant candidates of one
     event with square stencils in the DM-time plane, then clustering of the
     candidates in the DM-time plane keeping the highest-S/N one per cluster
@@ -28,13 +30,15 @@ It follows, in order:
 The paper fixes no rounding, reference frequency, S/N normalisation, boxcar
 index, candidate definition, stencil size or clustering parameter; the
 readings used here are listed in the module docstrings of oracle.dedisp,
-oracle.rfi and oracle.sift.
+oracle.rfi, oracle.robust and oracle.sift.
 """
 from .dedisp import *  # noqa: F401,F403
 from .dedisp import __all__ as _dedisp_all
 from .rfi import *  # noqa: F401,F403
 from .rfi import __all__ as _rfi_all
+from .robust import *  # noqa: F401,F403
+from .robust import __all__ as _robust_all
 from .sift import *  # noqa: F401,F403
 from .sift import __all__ as _sift_all
 
-__all__ = list(_dedisp_all) + list(_rfi_all) + list(_sift_all)
+__all__ = list(_dedisp_all) + list(_rfi_all) + list(_robust_all) + list(_sift_all)

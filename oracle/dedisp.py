@@ -183,10 +183,17 @@ class RowResult:
 
 
 def search_row(y: np.ndarray, widths: Sequence[int], n: int, cand_block: int,
-               threshold: float) -> RowResult:
-    """Single-pulse search of one dedispersed series (Section 2.1; R6-R9)."""
+               threshold: float, stats=None) -> RowResult:
+    """Single-pulse search of one dedispersed series (Section 2.1; R6-R9).
+    stats selects the noise estimate of the S/N (oracle.robust): None for
+    R7's moments, ("clip", k, iters) or ("mad",). s1, s2 are always the
+    plain moments of the owned samples."""
     s1, s2 = row_moments(y, n)
-    mu, sigma = mean_sigma(s1, s2, n)
+    if stats is None:
+        mu, sigma = mean_sigma(s1, s2, n)
+    else:
+        from .robust import robust_mean_sigma
+        mu, sigma = robust_mean_sigma(y, n, stats)
     snr = snr_matrix(y, widths, n, mu, sigma)
     bs, bj, bk = best_of(snr)
     cells, cands = [], []
@@ -217,6 +224,7 @@ class PlanSpec:
     widths: List[int]
     cand_block: int
     threshold: float
+    stats: Optional[tuple] = None   # noise estimate of the S/N (oracle.robust)
 
     @property
     def w_max(self) -> int:
@@ -239,7 +247,7 @@ class PlanSpec:
 
 
 def make_plan(freqs_mhz, t_samp, dm_list=None, ranges=None, widths=(),
-              cand_block=1024, threshold=7.0) -> PlanSpec:
+              cand_block=1024, threshold=7.0, stats=None) -> PlanSpec:
     """Plan from an explicit DM list (decimation 1) or from DM ranges
     (lo, hi, step, dec)."""
     if (dm_list is None) == (ranges is None):
@@ -253,7 +261,7 @@ def make_plan(freqs_mhz, t_samp, dm_list=None, ranges=None, widths=(),
             dms = dm_range_values(lo, hi, step)
             specs.append(RangeSpec(int(dec), dms, delay_table(freqs_mhz, dms, t_samp, int(dec))))
     return PlanSpec(np.asarray(freqs_mhz, dtype=np.float64), float(t_samp), specs,
-                    list(widths), int(cand_block), float(threshold))
+                    list(widths), int(cand_block), float(threshold), stats)
 
 
 def run(plan: PlanSpec, x: np.ndarray, rows: Optional[List[Sequence[int]]] = None,
@@ -271,7 +279,8 @@ def run(plan: PlanSpec, x: np.ndarray, rows: Optional[List[Sequence[int]]] = Non
         y = dedisperse_rows(xr, spec.delays, rr, length)
         res = None
         if search and plan.widths:
-            res = [search_row(y[k], plan.widths, owned[r], plan.cand_block, plan.threshold)
+            res = [search_row(y[k], plan.widths, owned[r], plan.cand_block, plan.threshold,
+                              plan.stats)
                    for k in range(len(rr))]
         out.append((rr, y, res))
     return out
