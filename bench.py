@@ -125,6 +125,65 @@ def sift_bench(sdd, torch, plan, out, dm_step: float, large: int):
             "seeded_list": {"candidates": m, "kept": kept_big, "ms": round(ms_big, 4)}}
 
 
+def rfi_bench(sdd, torch, plan, xt, planes, out, ws_unused, reps: int = 3):
+    """Time the RFI estimator on the step's chunk and the pre-conditioned step
+    (maps applied in the corner turn), both with HIP events on one stream."""
+    import ctypes as C
+    from paper_2605_03531_amd import _capi as A
+    L = A.lib()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        lut, mask, flags = plan.rfi_estimate(xt, stream=s)          # warm-up
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            lut, mask, flags = plan.rfi_estimate(xt, stream=s)
+        e1.record(s)
+        e1.synchronize()
+        est_ms = e0.elapsed_time(e1) / reps
+        plan.dedisperse_search(xt, planes=planes, out=out, lut=lut, time_mask=mask, stream=s)
+        s.synchronize()
+        A.check(L.sdd_profile_enable(1), "profile")
+        e0.record(s)
+        for _ in range(reps):
+            plan.dedisperse_search(xt, planes=planes, out=out, lut=lut, time_mask=mask, stream=s)
+        e1.record(s)
+        e1.synchronize()
+        step_ms = e0.elapsed_time(e1) / reps
+        ms, n = C.c_double(), C.c_int64()
+        A.check(L.sdd_profile_read(A.STAGES["corner_turn"], C.byref(ms), C.byref(n)), "read")
+        L.sdd_profile_enable(0)
+    return {"estimate_ms": round(est_ms, 3),
+            "flagged_channels": int(flags.sum().item()),
+            "flagged_samples": int((mask == 0).sum().item()),
+            "pre_step_ms": round(step_ms, 3),
+            "pre_corner_turn_ms": round(ms.value / max(n.value, 1), 4)}
+
+
+def robust_bench(sdd, torch, plan, xt, planes, out, ws, reps: int = 3):
+    """Search-stage time with each noise estimate (the step's chunk)."""
+    import ctypes as C
+    from paper_2605_03531_amd import _capi as A
+    L = A.lib()
+    res = {}
+    for name, args in (("moments", ("moments",)), ("clip_3sigma_3x", ("clip", 3.0, 3)),
+                       ("median_mad", ("mad",))):
+        plan.set_stats(*args)
+        plan.dedisperse_search(xt, planes=planes, out=out, workspace=ws)
+        torch.cuda.synchronize()
+        A.check(L.sdd_profile_enable(1), "profile")
+        for _ in range(reps):
+            plan.dedisperse_search(xt, planes=planes, out=out, workspace=ws)
+        torch.cuda.synchronize()
+        ms, n = C.c_double(), C.c_int64()
+        A.check(L.sdd_profile_read(A.STAGES["search"], C.byref(ms), C.byref(n)), "read")
+        L.sdd_profile_enable(0)
+        res[name] = {"search_ms": round(ms.value / max(n.value, 1), 4),
+                     "candidates": int(out.ncand.cpu()[0])}
+    plan.set_stats("moments")
+    return res
+
+
 def serve_bench(sdd, torch, nbeams: int, sat_chunks: int, rt_periods: int, max_batch: int,
                 nstreams: int, per_item: bool = True):
     """Streaming server with nbeams beams (1024/2048/4096 channels by beam
@@ -367,6 +426,10 @@ def main() -> int:
     }
     res["sift"] = sift_bench(sdd, torch, plan, out, float(w.dm_list[1] - w.dm_list[0]), 1 << 16)
     log(f"sift: {res['sift']}")
+    res["rfi"] = rfi_bench(sdd, torch, plan, xt, planes, out, ws)
+    log(f"rfi: {res['rfi']}")
+    res["robust_stats"] = robust_bench(sdd, torch, plan, xt, planes, out, ws)
+    log(f"robust statistics: {res['robust_stats']}")
     if args.copy_calibration:
         src = torch.empty(1 << 30, dtype=torch.uint8, device=dev).fill_(7)
         dst = torch.empty_like(src)

@@ -196,6 +196,21 @@ sdd_status sdd_plan_get_tile(const sdd_plan* plan, int32_t range, sdd_tile* out)
  * in the built menu or cannot hold the range's delay span. Results never
  * depend on the tile: the sums are exact. */
 sdd_status sdd_plan_set_tile(sdd_plan* plan, int32_t range, const sdd_tile* tile);
+/* Noise estimate (mu, sigma) of the search's S/N = (B - w*mu)/(sigma*sqrt(w))
+ * (Sections 2.1 and 3.3: the median resists outliers better than the mean):
+ *   SDD_STATS_MOMENTS    mean and population std of the owned samples
+ *                        (default);
+ *   SDD_STATS_CLIPPED    from those, `iters` passes keeping the samples with
+ *                        |y - mu| <= k * sigma (FP64) and recomputing mu and
+ *                        sigma from their exact integer moments (a pass that
+ *                        keeps none stops);
+ *   SDD_STATS_MEDIAN_MAD mu = lower median, sigma = 1.4826 * lower median of
+ *                        |y - mu| (exact selections).
+ * sdd_dm_stats then reports this mu and sigma as mean and std (n, s1, s2
+ * stay the plain moments). EINVAL on an unknown mode, or k <= 0 or iters
+ * outside 1..64 for SDD_STATS_CLIPPED. */
+enum { SDD_STATS_MOMENTS = 0, SDD_STATS_CLIPPED = 1, SDD_STATS_MEDIAN_MAD = 2 };
+sdd_status sdd_plan_set_stats(sdd_plan* plan, int32_t mode, double k, int32_t iters);
 /* Writes up to max menu entries to host_out; *n_out = menu size. */
 sdd_status sdd_tile_menu(sdd_tile* host_out, int32_t max, int32_t* n_out);
 /* Picks each 8-bit DM range's tile by timing every fitting menu shape on the

@@ -16,6 +16,7 @@ SDD_MAX_RANGES = 16
 SDD_MAX_WIDTHS = 32
 SDD_MAX_WMAX = 8192
 SDD_MAX_STENCILS = 8
+SDD_STATS_MOMENTS, SDD_STATS_CLIPPED, SDD_STATS_MEDIAN_MAD = 0, 1, 2
 SDD_CHAN_MAJOR, SDD_TIME_MAJOR = 0, 1
 
 STATUS = {0: "SDD_OK", -1: "SDD_EINVAL", -2: "SDD_ERANGE", -3: "SDD_ENOMEM",
@@ -122,6 +123,7 @@ _PROTOS = {
     "sdd_plan_get_tile": (i32, [vp, i32, C.POINTER(Tile)]),
     "sdd_plan_set_tile": (i32, [vp, i32, C.POINTER(Tile)]),
     "sdd_tile_menu": (i32, [C.POINTER(Tile), i32, C.POINTER(i32)]),
+    "sdd_plan_set_stats": (i32, [vp, i32, f64, i32]),
     "sdd_autotune": (i32, [vp, i64, C.c_char_p, vp]),
     "sdd_dedisperse": (i32, [vp, vp, i64, i64, C.POINTER(vp), C.POINTER(i64), vp, i64, vp]),
     "sdd_search_boxcar": (i32, [vp, C.POINTER(vp), C.POINTER(i64), i64, vp, vp, vp, i32, vp,

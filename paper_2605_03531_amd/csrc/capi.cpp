@@ -134,6 +134,11 @@ sdd_status run_search(const sdd_plan* p, const CallGeom& cg, const uint32_t* con
   a.threshold = p->threshold;
   a.cap = cap;
   a.max_boxcar = (int64_t)p->nchan * 255 * p->dec_max * p->w_max;
+  a.max_sample = (int64_t)p->nchan * 255 * p->dec_max;
+  a.stats_mode = p->stats_mode;
+  a.clip_k = p->clip_k;
+  a.clip_iters = p->clip_iters;
+  a.robust_off = cg.ws.robust_off;
   a.max_cells = 0;
   for (int32_t r = 0; r < a.nranges; ++r) {
     const Range& R = p->ranges[r];

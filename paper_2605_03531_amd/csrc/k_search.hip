@@ -422,6 +422,144 @@ __device__ inline bool better(double s, int64_t j, int w, double s2, int64_t j2,
   return w < w2;
 }
 
+// mu = S1/n, sigma = sqrt(n*S2 - S1^2)/n with the numerator formed exactly (128-bit).
+__device__ inline void mean_sigma_exact(uint64_t n, uint64_t s1, uint64_t s2, double* mu,
+                                        double* sigma) {
+  const uint64_t p_lo = n * s2, p_hi = __umul64hi(n, s2);
+  const uint64_t q_lo = s1 * s1, q_hi = __umul64hi(s1, s1);
+  const uint64_t d_lo = p_lo - q_lo;
+  const uint64_t d_hi = p_hi - q_hi - (p_lo < q_lo ? 1ull : 0ull);
+  *mu = (double)s1 / (double)n;
+  *sigma = 0.0;
+  if (d_hi != 0 || d_lo != 0) {
+    const double dd = (double)d_hi * 18446744073709551616.0 + (double)d_lo;
+    *sigma = sqrt(dd) / (double)n;
+  }
+}
+
+// ---- robust noise statistics (SDD_STATS_CLIPPED, SDD_STATS_MEDIAN_MAD) ----
+struct Robust {
+  double mu, sigma;
+  unsigned long long cnt, s1, s2, pad;
+};
+
+// Plain mean and sigma of every trial as the clipping's starting point.
+__global__ __launch_bounds__(256) void k_robust_init(SearchArgs a) {
+  const int32_t g = blockIdx.x * 256 + threadIdx.x;
+  if (g >= a.ndm_total) return;
+  const Moments m = reinterpret_cast<const Moments*>(a.ws + a.moments_off)[g];
+  Robust* rb = reinterpret_cast<Robust*>(a.ws + a.robust_off) + g;
+  const uint64_t n = (uint64_t)a.r[find_range(a, g)].n_owned;
+  double mu, sigma;
+  mean_sigma_exact(n, m.s1, m.s2, &mu, &sigma);
+  rb->mu = mu;
+  rb->sigma = sigma;
+  rb->cnt = rb->s1 = rb->s2 = 0ull;
+}
+
+// One clipping pass: exact moments of the owned samples with
+// |y - mu| <= k * sigma; blockIdx.y strides over the row.
+__global__ __launch_bounds__(256) void k_clip_acc(SearchArgs a) {
+  __shared__ unsigned long long red[3][4];
+  const int32_t g = blockIdx.x;
+  const int r = find_range(a, g);
+  const SearchRange& R = a.r[r];
+  const uint32_t* row = R.plane + (int64_t)(g - R.dm_offset) * R.pitch;
+  Robust* rb = reinterpret_cast<Robust*>(a.ws + a.robust_off) + g;
+  const double mu = rb->mu, lim = a.clip_k * rb->sigma;
+  unsigned long long c = 0, s1 = 0, s2 = 0;
+  for (int64_t j = (int64_t)blockIdx.y * 256 + threadIdx.x; j < R.n_owned;
+       j += (int64_t)gridDim.y * 256) {
+    const uint32_t y = row[j];
+    if (fabs((double)y - mu) <= lim) {
+      c += 1;
+      s1 += y;
+      s2 += (unsigned long long)y * y;
+    }
+  }
+  c = wave_sum_u64(c);
+  s1 = wave_sum_u64(s1);
+  s2 = wave_sum_u64(s2);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[0][w] = c;
+    red[1][w] = s1;
+    red[2][w] = s2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    atomicAdd(&rb->cnt, red[0][0] + red[0][1] + red[0][2] + red[0][3]);
+    atomicAdd(&rb->s1, red[1][0] + red[1][1] + red[1][2] + red[1][3]);
+    atomicAdd(&rb->s2, red[2][0] + red[2][1] + red[2][2] + red[2][3]);
+  }
+}
+
+// New mu, sigma from the kept samples (unchanged when none was kept).
+__global__ __launch_bounds__(256) void k_clip_update(SearchArgs a) {
+  const int32_t g = blockIdx.x * 256 + threadIdx.x;
+  if (g >= a.ndm_total) return;
+  Robust* rb = reinterpret_cast<Robust*>(a.ws + a.robust_off) + g;
+  if (rb->cnt > 0) {
+    double mu, sigma;
+    mean_sigma_exact(rb->cnt, rb->s1, rb->s2, &mu, &sigma);
+    rb->mu = mu;
+    rb->sigma = sigma;
+  }
+  rb->cnt = rb->s1 = rb->s2 = 0ull;
+}
+
+// Lower median of the owned samples (what == 0) or of |y - median| (what ==
+// 1) of one trial per workgroup: radix selection, 11 bits per pass.
+__global__ __launch_bounds__(1024) void k_row_select(SearchArgs a, int what, int passes) {
+  __shared__ uint32_t hist[2048];
+  __shared__ uint32_t s_prefix;
+  __shared__ int64_t s_k;
+  const int32_t g = blockIdx.x;
+  const int r = find_range(a, g);
+  const SearchRange& R = a.r[r];
+  const uint32_t* row = R.plane + (int64_t)(g - R.dm_offset) * R.pitch;
+  Robust* rb = reinterpret_cast<Robust*>(a.ws + a.robust_off) + g;
+  const int64_t n = R.n_owned;
+  const int64_t med = what ? (int64_t)rb->mu : 0;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    s_prefix = 0u;
+    s_k = (n - 1) / 2;
+  }
+  uint32_t hmask = 0u;
+  for (int ps = passes - 1; ps >= 0; --ps) {
+    for (int b = tid; b < 2048; b += 1024) hist[b] = 0u;
+    __syncthreads();
+    const uint32_t prefix = s_prefix;
+    const int sh = 11 * ps;
+    for (int64_t j = tid; j < n; j += 1024) {
+      int64_t v = row[j];
+      if (what) v = v > med ? v - med : med - v;
+      const uint32_t u = (uint32_t)v;
+      if ((u & hmask) == prefix) atomicAdd(&hist[(u >> sh) & 2047u], 1u);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int64_t kk = s_k;
+      int bin = 0;
+      for (; bin < 2047; ++bin) {
+        if (kk < (int64_t)hist[bin]) break;
+        kk -= hist[bin];
+      }
+      s_k = kk;
+      s_prefix = prefix | ((uint32_t)bin << sh);
+    }
+    __syncthreads();
+    hmask |= 2047u << sh;
+  }
+  if (tid == 0) {
+    if (what)
+      rb->sigma = 1.4826 * (double)s_prefix;
+    else
+      rb->mu = (double)s_prefix;
+  }
+}
+
 __global__ __launch_bounds__(kThreads) void k_rows(SearchArgs a) {
   __shared__ double rs[kThreads];
   __shared__ int64_t rj[kThreads];
@@ -436,16 +574,13 @@ __global__ __launch_bounds__(kThreads) void k_rows(SearchArgs a) {
   const CellKey* cres = reinterpret_cast<const CellKey*>(a.ws + a.cellres_off);
   CellBest* cbest = reinterpret_cast<CellBest*>(a.ws + a.cellbest_off);
   const uint64_t n = (uint64_t)R.n_owned;
-  // D = n*S2 - S1^2 exactly (128-bit), sigma = sqrt(D)/n
-  const uint64_t p_lo = n * m.s2, p_hi = __umul64hi(n, m.s2);
-  const uint64_t q_lo = m.s1 * m.s1, q_hi = __umul64hi(m.s1, m.s1);
-  const uint64_t d_lo = p_lo - q_lo;
-  const uint64_t d_hi = p_hi - q_hi - (p_lo < q_lo ? 1ull : 0ull);
-  const double mu = (double)m.s1 / (double)n;
-  double sigma = 0.0;
-  if (d_hi != 0 || d_lo != 0) {
-    const double dd = (double)d_hi * 18446744073709551616.0 + (double)d_lo;
-    sigma = sqrt(dd) / (double)n;
+  double mu, sigma;
+  if (a.stats_mode == SDD_STATS_MOMENTS) {
+    mean_sigma_exact(n, m.s1, m.s2, &mu, &sigma);
+  } else {
+    const Robust* rb = reinterpret_cast<const Robust*>(a.ws + a.robust_off) + g;
+    mu = rb->mu;
+    sigma = rb->sigma;
   }
   if (tid == 0 && a.stats) {
     sdd_dm_stats st;
@@ -630,6 +765,20 @@ hipError_t launch_search(const SearchArgs& a, hipStream_t s) {
         (unsigned)(a.max_cells < 1 ? 1 : (a.max_cells > 65535 ? 65535 : a.max_cells));
     const size_t lds = (size_t)(kSub + a.w_max) * sizeof(uint32_t);
     hipLaunchKernelGGL(k_cells, dim3((unsigned)a.ndm_total, gy), dim3(kThreads), lds, s, a);
+  }
+  if (a.stats_mode == SDD_STATS_CLIPPED) {
+    const dim3 gr((unsigned)((a.ndm_total + 255) / 256));
+    hipLaunchKernelGGL(k_robust_init, gr, dim3(256), 0, s, a);
+    for (int it = 0; it < a.clip_iters; ++it) {
+      hipLaunchKernelGGL(k_clip_acc, dim3((unsigned)a.ndm_total, 16), dim3(256), 0, s, a);
+      hipLaunchKernelGGL(k_clip_update, gr, dim3(256), 0, s, a);
+    }
+  } else if (a.stats_mode == SDD_STATS_MEDIAN_MAD) {
+    int bits = 1;
+    while (bits < 32 && (a.max_sample >> bits) != 0) ++bits;
+    const int passes = (bits + 10) / 11;
+    hipLaunchKernelGGL(k_row_select, dim3((unsigned)a.ndm_total), dim3(1024), 0, s, a, 0, passes);
+    hipLaunchKernelGGL(k_row_select, dim3((unsigned)a.ndm_total), dim3(1024), 0, s, a, 1, passes);
   }
   hipLaunchKernelGGL(k_rows, dim3((unsigned)a.ndm_total), dim3(kThreads), 0, s, a);
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, a);

@@ -203,6 +203,7 @@ sdd_status plan_geometry(const sdd_plan* p, int64_t nsamp_in, CallGeom* out) {
     ws.cellbest_off = take(cells_total * 16);
     ws.rowcnt_off = take((int64_t)p->ndm_total * 4);
     ws.rowoff_off = take(((int64_t)p->ndm_total + 1) * 4);
+    ws.robust_off = take((int64_t)p->ndm_total * 48);
   }
   ws.total = off;
   for (size_t r = 0; r < p->ranges.size(); ++r) {
@@ -451,6 +452,22 @@ extern "C" sdd_status sdd_plan_set_tile(sdd_plan* p, int32_t r, const sdd_tile* 
     p->ranges[k].tile_span = spans[k - r0];
   }
   p->version++;
+  return SDD_OK;
+}
+
+extern "C" sdd_status sdd_plan_set_stats(sdd_plan* p, int32_t mode, double k, int32_t iters) {
+  clear_error();
+  if (!p) SDD_FAIL(SDD_EINVAL, "null plan");
+  if (mode != SDD_STATS_MOMENTS && mode != SDD_STATS_CLIPPED && mode != SDD_STATS_MEDIAN_MAD)
+    SDD_FAIL(SDD_EINVAL, "unknown statistics mode %d", mode);
+  if (mode == SDD_STATS_CLIPPED && (!(k > 0.0) || !std::isfinite(k) || iters < 1 || iters > 64))
+    SDD_FAIL(SDD_EINVAL, "clipping needs k > 0 and 1..64 iterations");
+  p->stats_mode = mode;
+  if (mode == SDD_STATS_CLIPPED) {
+    p->clip_k = k;
+    p->clip_iters = iters;
+  }
+  p->version++;  // cached batch graphs hold the old search arguments
   return SDD_OK;
 }
 

@@ -72,11 +72,12 @@ struct WsLayout {
   std::vector<int64_t> dec_off, dec_pitch, dec_len;  // u16 [C][pitch] each
   int64_t plane_off[SDD_MAX_RANGES] = {0};       // library planes (with_planes only)
   int64_t plane_pitch[SDD_MAX_RANGES] = {0};     // elements
-  int64_t cellres_off = 0;   // [sum_r ndm_r * ncells_r * nw] {u32 B, i32 j}
+  int64_t cellres_off = 0;   // [sum_r ndm_r * ncells_r * nw] u64 (B << 32) | ~(j - cell start)
   int64_t moments_off = 0;   // [ndm_total] {u64 s1, u64 s2}
   int64_t cellbest_off = 0;  // [sum_r ndm_r * ncells_r] {f64 snr, i32 j, i32 w}
   int64_t rowcnt_off = 0;    // [ndm_total] i32
   int64_t rowoff_off = 0;    // [ndm_total + 1] i32
+  int64_t robust_off = 0;    // [ndm_total] {f64 mu, f64 sigma, u64 cnt, s1, s2, pad}
   int64_t search_cells = 0;  // sum_r ndm_r * ncells_r
   int64_t total = 0;         // bytes without library planes
   int64_t total_planes = 0;  // bytes with library planes
@@ -102,6 +103,10 @@ struct sdd_plan {
   int64_t overlap = 0;
   int32_t ndm_total = 0;
   int32_t dec_max = 1;
+  // noise estimate of the search's S/N (sdd_plan_set_stats)
+  int32_t stats_mode = 0;
+  double clip_k = 3.0;
+  int32_t clip_iters = 3;
 
   uint64_t id = 0;       // process-unique, never reused
   uint64_t version = 0;  // bumped whenever the tile choice changes
@@ -199,6 +204,11 @@ struct SearchArgs {
   int32_t max_cells;     // max_r ncells_r
   int32_t cap;
   int64_t max_boxcar;    // bound on any boxcar sum: nchan * 255 * dec_max * w_max
+  int64_t max_sample;    // bound on any plane value: nchan * 255 * dec_max
+  int32_t stats_mode;    // SDD_STATS_*
+  int32_t clip_iters;
+  double clip_k;
+  int64_t robust_off;
   uint8_t* ws;           // workspace base
   int64_t cellres_off, moments_off, cellbest_off, rowcnt_off, rowoff_off;
   sdd_dm_best* best;

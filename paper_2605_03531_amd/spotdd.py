@@ -135,6 +135,14 @@ class Plan:
     def handle(self):
         return self._p
 
+    def set_stats(self, mode: str = "moments", k: float = 3.0, iters: int = 3) -> None:
+        """Noise estimate of the search's S/N: "moments" (default), "clip"
+        (sigma-clipped, k and iters) or "mad" (median and 1.4826 * MAD)."""
+        m = {"moments": A.SDD_STATS_MOMENTS, "clip": A.SDD_STATS_CLIPPED,
+             "mad": A.SDD_STATS_MEDIAN_MAD}[mode]
+        A.check(A.lib().sdd_plan_set_stats(self._p, m, float(k), int(iters)),
+                "sdd_plan_set_stats")
+
     def delays(self, r: int = 0) -> np.ndarray:
         out = np.empty((self.ndm[r], self.nchan), dtype=np.int32)
         A.check(A.lib().sdd_plan_delays(self._p, r, out.ctypes.data_as(C.POINTER(C.c_int32))),

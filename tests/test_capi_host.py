@@ -226,3 +226,16 @@ def test_rfi_entry_points_validate_before_touching_the_device():
     best = (C.c_byte * 64)()
     assert L.sdd_dedisperse_search_pre(p.handle, 1, T, 3, None, None, None, None, best, None,
                                        None, 0, best, 1, nb.value - 1, None) == A.SDD_ENOMEM
+
+
+def test_set_stats_validates():
+    L = A.lib()
+    p = sdd.Plan([500.0, 300.0], 1e-3, dm_list=[0.0, 5.0], widths=[1])
+    assert L.sdd_plan_set_stats(p.handle, 7, 3.0, 3) == A.SDD_EINVAL
+    assert L.sdd_plan_set_stats(p.handle, A.SDD_STATS_CLIPPED, 0.0, 3) == A.SDD_EINVAL
+    assert L.sdd_plan_set_stats(p.handle, A.SDD_STATS_CLIPPED, 3.0, 0) == A.SDD_EINVAL
+    assert L.sdd_plan_set_stats(p.handle, A.SDD_STATS_CLIPPED, 3.0, 65) == A.SDD_EINVAL
+    assert L.sdd_plan_set_stats(None, 0, 0.0, 0) == A.SDD_EINVAL
+    p.set_stats("clip", 2.5, 4)
+    p.set_stats("mad")
+    p.set_stats()
