@@ -183,11 +183,15 @@ class RowResult:
 
 
 def search_row(y: np.ndarray, widths: Sequence[int], n: int, cand_block: int,
-               threshold: float, stats=None) -> RowResult:
+               threshold: float, stats=None, dered=None) -> RowResult:
     """Single-pulse search of one dedispersed series (Section 2.1; R6-R9).
     stats selects the noise estimate of the S/N (oracle.robust): None for
     R7's moments, ("clip", k, iters) or ("mad",). s1, s2 are always the
-    plain moments of the owned samples."""
+    plain moments of the owned samples of the searched series. dered = (D, h, M) searches the
+    de-reddened series instead (oracle.robust, Q4; M the full scale)."""
+    if dered is not None:
+        from .robust import dereddened
+        y = dereddened(y, n + max(widths) - 1, dered[0], dered[1], dered[2])
     s1, s2 = row_moments(y, n)
     if stats is None:
         mu, sigma = mean_sigma(s1, s2, n)
@@ -225,6 +229,7 @@ class PlanSpec:
     cand_block: int
     threshold: float
     stats: Optional[tuple] = None   # noise estimate of the S/N (oracle.robust)
+    dered: Optional[tuple] = None   # (D, h) de-reddening of the searched series
 
     @property
     def w_max(self) -> int:
@@ -247,7 +252,7 @@ class PlanSpec:
 
 
 def make_plan(freqs_mhz, t_samp, dm_list=None, ranges=None, widths=(),
-              cand_block=1024, threshold=7.0, stats=None) -> PlanSpec:
+              cand_block=1024, threshold=7.0, stats=None, dered=None) -> PlanSpec:
     """Plan from an explicit DM list (decimation 1) or from DM ranges
     (lo, hi, step, dec)."""
     if (dm_list is None) == (ranges is None):
@@ -261,7 +266,8 @@ def make_plan(freqs_mhz, t_samp, dm_list=None, ranges=None, widths=(),
             dms = dm_range_values(lo, hi, step)
             specs.append(RangeSpec(int(dec), dms, delay_table(freqs_mhz, dms, t_samp, int(dec))))
     return PlanSpec(np.asarray(freqs_mhz, dtype=np.float64), float(t_samp), specs,
-                    list(widths), int(cand_block), float(threshold), stats)
+                    list(widths), int(cand_block), float(threshold), stats,
+                    None if dered is None else (int(dered[0]), int(dered[1])))
 
 
 def run(plan: PlanSpec, x: np.ndarray, rows: Optional[List[Sequence[int]]] = None,
@@ -279,8 +285,11 @@ def run(plan: PlanSpec, x: np.ndarray, rows: Optional[List[Sequence[int]]] = Non
         y = dedisperse_rows(xr, spec.delays, rr, length)
         res = None
         if search and plan.widths:
+            dr = None
+            if plan.dered is not None:
+                dr = (plan.dered[0], plan.dered[1], len(plan.freqs_mhz) * 255 * spec.dec)
             res = [search_row(y[k], plan.widths, owned[r], plan.cand_block, plan.threshold,
-                              plan.stats)
+                              plan.stats, dr)
                    for k in range(len(rr))]
         out.append((rr, y, res))
     return out

@@ -19,6 +19,19 @@ Readings:
   Q3  Either replaces (mu, sigma) of R7 in S/N = (B - w*mu)/(sigma*sqrt(w));
       sigma == 0 still means no candidates. The boxcar sums, cells, ties and
       threshold are unchanged.
+  Q4  De-reddening by running-median subtraction (Section 3.3), with the
+      median window moved in strides of a block of D samples (D = 1 would be
+      the per-sample running median): block k of the series (samples
+      [kD, kD + D) of its L = N_r + w_max - 1 columns) gets
+      base_k = lower median of the samples in blocks k - h .. k + h (clipped
+      to the series; window (2h + 1) D, which the paper wants above twice the
+      widest pulse), and the searched series is
+      y''[j] = clip(y[j] - base_{j // D} + M // 2, 0, M), M = nchan * 255 * dec
+      the plane's full scale: re-centred at half scale so it stays a
+      non-negative integer within every bound of the plain plane (the clip
+      only acts on samples more than M / 2 from their baseline; the constant
+      moves mu and leaves sigma and the S/N alone). The moments, the noise
+      estimate and the boxcar sums are all taken on y''.
 """
 from __future__ import annotations
 
@@ -27,7 +40,8 @@ from typing import Tuple
 
 import numpy as np
 
-__all__ = ["clipped_moments", "median_mad", "robust_mean_sigma"]
+__all__ = ["clipped_moments", "median_mad", "robust_mean_sigma", "block_baseline",
+           "dereddened"]
 
 MAD_SCALE = 1.4826
 
@@ -73,3 +87,22 @@ def robust_mean_sigma(y: np.ndarray, n: int, mode) -> Tuple[float, float]:
     if mode[0] == "mad":
         return median_mad(y, n)
     raise ValueError(f"unknown statistics mode {mode!r}")
+
+
+def block_baseline(y: np.ndarray, L: int, D: int, h: int) -> np.ndarray:
+    """base_k for every block of the series y[0:L] (Q4)."""
+    nb = (L + D - 1) // D
+    v = y[:L].astype(np.int64)
+    out = np.empty(nb, dtype=np.int64)
+    for k in range(nb):
+        w = np.sort(v[max(0, (k - h) * D):min(L, (k + h + 1) * D)])
+        out[k] = w[(len(w) - 1) // 2]
+    return out
+
+
+def dereddened(y: np.ndarray, L: int, D: int, h: int, M: int) -> np.ndarray:
+    """y''[j] = clip(y[j] - base_{j // D} + M // 2, 0, M) for j < L (Q4)."""
+    base = block_baseline(y, L, D, h)
+    j = np.arange(L)
+    return np.clip(y[:L].astype(np.int64) - base[j // D] + M // 2, 0, M)
+

@@ -59,3 +59,52 @@ def test_search_row_uses_the_chosen_statistics():
     assert rob.best[1:] == base.best[1:] == (1000, 4)
     med, sig = median_mad(y, 4097)
     assert rob.mean == med and rob.std == sig
+
+
+def test_block_baseline_with_unit_blocks_is_the_running_median():
+    """D = 1: the baseline is the per-sample running median (window 2h+1,
+    clipped at the ends), i.e. scipy's median filter in the interior."""
+    from scipy.ndimage import median_filter
+    g = np.random.Generator(np.random.PCG64(9))
+    y = g.integers(0, 1000, 3000)
+    base = oracle.block_baseline(y, 3000, 1, 10)
+    ref = median_filter(y, size=21)
+    assert np.array_equal(base[10:-10], ref[10:-10])
+
+
+def test_dereddening_removes_a_slow_baseline_and_keeps_the_pulse():
+    g = np.random.Generator(np.random.PCG64(10))
+    L = 1 << 14
+    t = np.arange(L)
+    y = np.round(g.normal(1000.0, 10.0, L) + 200.0 * np.sin(2 * np.pi * t / 6000.0))
+    y = y.astype(np.int64)
+    y[9000:9008] += 150
+    M = 4096 * 255
+    d = oracle.dereddened(y, L, 64, 2, M) - M // 2
+    # the slow wave is gone (its 200-count swing left within a few counts)
+    assert np.abs(np.convolve(d, np.ones(512) / 512, "valid")).max() < 20.0
+    plain = oracle.search_row(y, [1, 8], L - 7, 1024, 6.0)
+    red = oracle.search_row(y, [1, 8], L - 7, 1024, 6.0, dered=(64, 2, M))
+    assert red.best[1:] == (9000, 8)
+    assert red.best[0] > 5.0 * plain.best[0] or plain.best[1] != 9000
+
+
+def test_offset_leaves_every_snr_unchanged():
+    """The half-scale offset only moves mu: two full scales large enough that
+    the clip never acts give the same S/N, cells and candidates."""
+    g = np.random.Generator(np.random.PCG64(11))
+    y = g.integers(100, 900, 5000)
+    a = oracle.search_row(y, [1, 2, 4], 4997, 512, 3.0, dered=(16, 1, 2000))
+    b = oracle.search_row(y, [1, 2, 4], 4997, 512, 3.0, dered=(16, 1, 777777))
+    assert a.best[1:] == b.best[1:] and abs(a.best[0] - b.best[0]) < 1e-9
+    assert [c[1:] for c in a.cands] == [c[1:] for c in b.cands]
+
+
+def test_dereddened_clip_bounds():
+    """Samples more than M/2 below / above their baseline clip to 0 / M."""
+    y = np.full(256, 500, dtype=np.int64)
+    y[100] = 0
+    y[200] = 1000
+    d = oracle.dereddened(y, 256, 64, 1, 600)
+    assert d[100] == 0 and d[200] == 600 and d[0] == 300
+    assert np.all((d >= 0) & (d <= 600))
