@@ -161,25 +161,33 @@ def rfi_bench(sdd, torch, plan, xt, planes, out, ws_unused, reps: int = 3):
 
 
 def robust_bench(sdd, torch, plan, xt, planes, out, ws, reps: int = 3):
-    """Search-stage time with each noise estimate (the step's chunk)."""
+    """Search-stage time with each noise estimate, and with running-median
+    de-reddening (256-sample blocks, 1280-sample window) (the step's chunk)."""
     import ctypes as C
     from paper_2605_03531_amd import _capi as A
     L = A.lib()
     res = {}
-    for name, args in (("moments", ("moments",)), ("clip_3sigma_3x", ("clip", 3.0, 3)),
-                       ("median_mad", ("mad",))):
+    for name, args, dered in (("moments", ("moments",), None),
+                              ("clip_3sigma_3x", ("clip", 3.0, 3), None),
+                              ("median_mad", ("mad",), None),
+                              ("dered_256x5_moments", ("moments",), (256, 2)),
+                              ("dered_256x5_median_mad", ("mad",), (256, 2))):
         plan.set_stats(*args)
-        plan.dedisperse_search(xt, planes=planes, out=out, workspace=ws)
+        if dered is not None:
+            plan.set_dereddening(*dered)
+        w = ws if dered is None else None  # the de-reddening baselines need more workspace
+        plan.dedisperse_search(xt, planes=planes, out=out, workspace=w)
         torch.cuda.synchronize()
         A.check(L.sdd_profile_enable(1), "profile")
         for _ in range(reps):
-            plan.dedisperse_search(xt, planes=planes, out=out, workspace=ws)
+            plan.dedisperse_search(xt, planes=planes, out=out, workspace=w)
         torch.cuda.synchronize()
         ms, n = C.c_double(), C.c_int64()
         A.check(L.sdd_profile_read(A.STAGES["search"], C.byref(ms), C.byref(n)), "read")
         L.sdd_profile_enable(0)
         res[name] = {"search_ms": round(ms.value / max(n.value, 1), 4),
                      "candidates": int(out.ncand.cpu()[0])}
+        plan.set_dereddening(0)
     plan.set_stats("moments")
     return res
 

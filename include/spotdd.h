@@ -211,6 +211,23 @@ sdd_status sdd_plan_set_tile(sdd_plan* plan, int32_t range, const sdd_tile* tile
  * outside 1..64 for SDD_STATS_CLIPPED. */
 enum { SDD_STATS_MOMENTS = 0, SDD_STATS_CLIPPED = 1, SDD_STATS_MEDIAN_MAD = 2 };
 sdd_status sdd_plan_set_stats(sdd_plan* plan, int32_t mode, double k, int32_t iters);
+/* Running-median de-reddening of every searched series (Section 3.3: the
+ * slowly varying baseline is removed by subtracting a running median whose
+ * window exceeds twice the widest pulse). The window moves in strides of a
+ * block of `block` samples: block k (samples [k*block, (k+1)*block) of the
+ * trial's N_r + w_max - 1 columns) gets base_k = lower median of the samples
+ * of blocks k-half .. k+half (clipped to the series), and the search (its
+ * moments, noise estimate, boxcar sums and candidates) runs on
+ *   y''[j] = clip(y[j] - base_{j / block} + M/2, 0, M),
+ * M = nchan * 255 * dec the range's full scale (integer M/2; the clip acts
+ * only on samples more than M/2 from their baseline, and the offset moves
+ * mu, not sigma or the S/N). The DM-time planes themselves are left as
+ * dedispersed. sdd_dm_stats then reports the moments of y''.
+ * block = 0 turns it off. EINVAL unless block is a power of two in 64..4096,
+ * half >= 1, (2*half+1)*block <= 4096 and > 2 * the widest boxcar, and the
+ * plan has boxcar widths; ERANGE if nchan * 255 * dec_max >= 2^30. The
+ * workspace grows by ndm_total * ceil(max columns / block) * 4 bytes. */
+sdd_status sdd_plan_set_dereddening(sdd_plan* plan, int32_t block, int32_t half);
 /* Writes up to max menu entries to host_out; *n_out = menu size. */
 sdd_status sdd_tile_menu(sdd_tile* host_out, int32_t max, int32_t* n_out);
 /* Picks each 8-bit DM range's tile by timing every fitting menu shape on the

@@ -124,6 +124,7 @@ _PROTOS = {
     "sdd_plan_set_tile": (i32, [vp, i32, C.POINTER(Tile)]),
     "sdd_tile_menu": (i32, [C.POINTER(Tile), i32, C.POINTER(i32)]),
     "sdd_plan_set_stats": (i32, [vp, i32, f64, i32]),
+    "sdd_plan_set_dereddening": (i32, [vp, i32, i32]),
     "sdd_autotune": (i32, [vp, i64, C.c_char_p, vp]),
     "sdd_dedisperse": (i32, [vp, vp, i64, i64, C.POINTER(vp), C.POINTER(i64), vp, i64, vp]),
     "sdd_search_boxcar": (i32, [vp, C.POINTER(vp), C.POINTER(i64), i64, vp, vp, vp, i32, vp,

@@ -139,6 +139,14 @@ sdd_status run_search(const sdd_plan* p, const CallGeom& cg, const uint32_t* con
   a.clip_k = p->clip_k;
   a.clip_iters = p->clip_iters;
   a.robust_off = cg.ws.robust_off;
+  a.dered_shift = 0;
+  if (p->dered_block > 0) {
+    while ((1 << a.dered_shift) < p->dered_block) ++a.dered_shift;
+    a.dered_half = p->dered_half;
+    a.dered_elems = (int32_t)(((int64_t)(2 * p->dered_half + 1) * p->dered_block + 63) / 64);
+    a.dered_nb = (int32_t)cg.ws.dered_nb;
+    a.dered_off = cg.ws.dered_off;
+  }
   a.max_cells = 0;
   for (int32_t r = 0; r < a.nranges; ++r) {
     const Range& R = p->ranges[r];
@@ -148,6 +156,7 @@ sdd_status run_search(const sdd_plan* p, const CallGeom& cg, const uint32_t* con
     a.r[r].ndm = R.ndm();
     a.r[r].dm_offset = R.dm_offset;
     a.r[r].ncells = (int32_t)cg.g.ncells[r];
+    a.r[r].full_scale = (int32_t)std::min<int64_t>((int64_t)p->nchan * 255 * R.dec, INT32_MAX);
     a.r[r].cell_base = cg.cell_base[r];
     a.max_cells = std::max(a.max_cells, a.r[r].ncells);
   }

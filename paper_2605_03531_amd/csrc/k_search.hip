@@ -13,6 +13,9 @@
 //              its candidate count (S/N > threshold).
 //   k_scan     exclusive scan of the per-trial counts (one workgroup).
 //   k_compact  per trial: writes its candidates in sample order at its offset.
+// With de-reddening (Section 3.3) k_dered_base first finds each trial's
+// block baselines (running median in block strides), and every kernel that
+// reads the plane searches clip(y - base + M/2, 0, M) instead of y.
 // Every step is deterministic: integer sums are order-free and every
 // selection has a total tie order.
 #include <algorithm>
@@ -81,6 +84,23 @@ __device__ inline T block_exclusive_scan(T v, T* tmp, T* total) {
   return off + inc - v;
 }
 
+// ---- de-reddening (running-median subtraction, Section 3.3) ---------------
+// The searched sample: y - base + M/2 clipped to [0, M], M the plane's full
+// scale, so every bound of the plain plane still holds.
+__device__ inline uint32_t dered(uint32_t y, uint32_t base, int32_t M) {
+  const int32_t t = (int32_t)y - (int32_t)base + (M >> 1);
+  return (uint32_t)min(max(t, 0), M);
+}
+__device__ inline const uint32_t* dered_base(const SearchArgs& a, int32_t g) {
+  return reinterpret_cast<const uint32_t*>(a.ws + a.dered_off) + (int64_t)g * a.dered_nb;
+}
+// Sample j of a trial's searched series.
+__device__ inline uint32_t searched(const SearchArgs& a, const SearchRange& R,
+                                    const uint32_t* base, const uint32_t* row, int64_t j) {
+  const uint32_t y = row[j];
+  return a.dered_shift ? dered(y, base[j >> a.dered_shift], R.full_scale) : y;
+}
+
 __global__ __launch_bounds__(256) void k_zero_u64(unsigned long long* p, int64_t n) {
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n) p[k] = 0ull;
@@ -97,6 +117,7 @@ __global__ __launch_bounds__(kThreads) void k_cells(SearchArgs a) {
   const SearchRange& R = a.r[r];
   const int32_t i = g - R.dm_offset;
   const uint32_t* row = R.plane + (int64_t)i * R.pitch;
+  const uint32_t* dbase = dered_base(a, g);
   Moments* mom = reinterpret_cast<Moments*>(a.ws + a.moments_off);
   CellKey* cres = reinterpret_cast<CellKey*>(a.ws + a.cellres_off);
   unsigned long long s1 = 0, s2 = 0;
@@ -108,7 +129,7 @@ __global__ __launch_bounds__(kThreads) void k_cells(SearchArgs a) {
       const int cnt = (int)min((int64_t)kSub, je - s0);
       const int len = cnt + a.w_max - 1;
       __syncthreads();  // previous users of sm / run_best init
-      for (int k = tid; k < len; k += kThreads) sm[k] = row[s0 + k];
+      for (int k = tid; k < len; k += kThreads) sm[k] = searched(a, R, dbase, row, s0 + k);
       __syncthreads();
       for (int k = tid; k < cnt; k += kThreads) {
         unsigned long long v = sm[k];
@@ -269,7 +290,8 @@ __device__ inline void read_shifted(const uint32_t* E, int lane, int w, uint32_t
 
 // NARROW: every boxcar sum is below 2^28, so (B << 4) | (15 - t) orders by
 // sum, then by earlier start, and one v_max per start keeps both.
-template <bool NARROW>
+// DERED: the lane's 16 samples lie in one de-reddening block (D >= 64).
+template <bool NARROW, bool DERED>
 __global__ __launch_bounds__(64) void k_seg(SearchArgs a) {
   extern __shared__ __attribute__((aligned(16))) uint32_t E[];  // kSeg + H + 4
   const int lane = threadIdx.x;
@@ -281,6 +303,7 @@ __global__ __launch_bounds__(64) void k_seg(SearchArgs a) {
   const int64_t cols = n + a.w_max - 1;
   const int32_t nseg = (int32_t)((n + kSeg - 1) / kSeg);
   const uint32_t* row = R.plane + (int64_t)i * R.pitch;
+  const uint32_t* dbase = dered_base(a, g);
   const int32_t H = (a.w_max - 1 + 15) & ~15;  // halo samples
   const int32_t segs_per_cell = a.cand_block / kSeg;
   CellKey* cres = reinterpret_cast<CellKey*>(a.ws + a.cellres_off);
@@ -296,6 +319,13 @@ __global__ __launch_bounds__(64) void k_seg(SearchArgs a) {
     const bool full = j0 + kSeg <= n;
     uint32_t y[16], e[16];
     load16(row, jl, cols, y);
+    if constexpr (DERED) {
+      if (jl < cols) {
+        const uint32_t b = dbase[jl >> a.dered_shift];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) y[t] = dered(y[t], b, R.full_scale);
+      }
+    }
     if (full || jl + 16 <= n) {
       if constexpr (NARROW) {
         // samples are below 2^28 / w_max <= 2^28: 16 of them fit 32 bits
@@ -329,9 +359,17 @@ __global__ __launch_bounds__(64) void k_seg(SearchArgs a) {
     if (H > 0) {
       uint32_t h[16], he[16];
       const bool hl = 16 * lane < H;
-      if (hl)
-        load16(row, j0 + kSeg + 16 * lane, cols, h);
-      else
+      if (hl) {
+        const int64_t jh = j0 + kSeg + 16 * lane;
+        load16(row, jh, cols, h);
+        if constexpr (DERED) {
+          if (jh < cols) {
+            const uint32_t b = dbase[jh >> a.dered_shift];
+#pragma unroll
+            for (int t = 0; t < 16; ++t) h[t] = dered(h[t], b, R.full_scale);
+          }
+        }
+      } else
 #pragma unroll
         for (int t = 0; t < 16; ++t) h[t] = 0u;
       const uint32_t htot = wave_prefix16(h, total, he);
@@ -414,6 +452,57 @@ __global__ __launch_bounds__(64) void k_seg(SearchArgs a) {
   }
 }
 
+// Baselines of one trial's de-reddening blocks: block k gets the lower median
+// of the samples of blocks k-h..k+h (clipped to the L = N_r + w_max - 1
+// columns). One wavefront per block: the window sits in registers (lane l
+// holds samples lo + 64 e + l, e < E; absent ones read all-ones, above any
+// sample), and a bisection on the value between the window's minimum and
+// maximum counts the samples <= mid with ballots. Exact: the result is the
+// smallest v with more than rank samples <= v, a sample of the window.
+template <int E>
+__global__ __launch_bounds__(256) void k_dered_base(SearchArgs a) {
+  const int32_t g = blockIdx.x;
+  const int r = find_range(a, g);
+  const SearchRange& R = a.r[r];
+  const uint32_t* row = R.plane + (int64_t)(g - R.dm_offset) * R.pitch;
+  const int64_t L = R.n_owned + a.w_max - 1;
+  const int sh = a.dered_shift, h = a.dered_half;
+  const int64_t nb = (L + (1 << sh) - 1) >> sh;
+  uint32_t* base = reinterpret_cast<uint32_t*>(a.ws + a.dered_off) + (int64_t)g * a.dered_nb;
+  const int lane = threadIdx.x & 63;
+  for (int64_t k = (int64_t)blockIdx.y * 4 + (threadIdx.x >> 6); k < nb;
+       k += (int64_t)gridDim.y * 4) {
+    const int64_t lo = max<int64_t>(0, (k - h) << sh);
+    const int64_t hi = min<int64_t>(L, (k + h + 1) << sh);
+    uint32_t x[E];
+    uint32_t mn = 0xffffffffu, mx = 0u;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int64_t j = lo + 64 * e + lane;
+      x[e] = j < hi ? row[j] : 0xffffffffu;
+      if (j < hi) {
+        mn = min(mn, x[e]);
+        mx = max(mx, x[e]);
+      }
+    }
+    mn = ~wave_max_u32(~mn);
+    mx = wave_max_u32(mx);
+    const int64_t rank = (hi - lo - 1) / 2;
+    uint32_t vlo = mn, vhi = mx;
+    while (vlo < vhi) {
+      const uint32_t mid = vlo + (vhi - vlo) / 2;
+      int64_t c = 0;
+#pragma unroll
+      for (int e = 0; e < E; ++e) c += __popcll(__ballot(x[e] <= mid));
+      if (c > rank)
+        vhi = mid;
+      else
+        vlo = mid + 1;
+    }
+    if (lane == 0) base[k] = vlo;
+  }
+}
+
 // true if (s, j, w) comes before (s2, j2, w2): higher S/N, then smaller j,
 // then smaller w.
 __device__ inline bool better(double s, int64_t j, int w, double s2, int64_t j2, int w2) {
@@ -465,12 +554,13 @@ __global__ __launch_bounds__(256) void k_clip_acc(SearchArgs a) {
   const int r = find_range(a, g);
   const SearchRange& R = a.r[r];
   const uint32_t* row = R.plane + (int64_t)(g - R.dm_offset) * R.pitch;
+  const uint32_t* dbase = dered_base(a, g);
   Robust* rb = reinterpret_cast<Robust*>(a.ws + a.robust_off) + g;
   const double mu = rb->mu, lim = a.clip_k * rb->sigma;
   unsigned long long c = 0, s1 = 0, s2 = 0;
   for (int64_t j = (int64_t)blockIdx.y * 256 + threadIdx.x; j < R.n_owned;
        j += (int64_t)gridDim.y * 256) {
-    const uint32_t y = row[j];
+    const uint32_t y = searched(a, R, dbase, row, j);
     if (fabs((double)y - mu) <= lim) {
       c += 1;
       s1 += y;
@@ -518,6 +608,7 @@ __global__ __launch_bounds__(1024) void k_row_select(SearchArgs a, int what, int
   const int r = find_range(a, g);
   const SearchRange& R = a.r[r];
   const uint32_t* row = R.plane + (int64_t)(g - R.dm_offset) * R.pitch;
+  const uint32_t* dbase = dered_base(a, g);
   Robust* rb = reinterpret_cast<Robust*>(a.ws + a.robust_off) + g;
   const int64_t n = R.n_owned;
   const int64_t med = what ? (int64_t)rb->mu : 0;
@@ -533,7 +624,7 @@ __global__ __launch_bounds__(1024) void k_row_select(SearchArgs a, int what, int
     const uint32_t prefix = s_prefix;
     const int sh = 11 * ps;
     for (int64_t j = tid; j < n; j += 1024) {
-      int64_t v = row[j];
+      int64_t v = searched(a, R, dbase, row, j);
       if (what) v = v > med ? v - med : med - v;
       const uint32_t u = (uint32_t)v;
       if ((u & hmask) == prefix) atomicAdd(&hist[(u >> sh) & 2047u], 1u);
@@ -734,6 +825,34 @@ hipError_t launch_search(const SearchArgs& a, hipStream_t s) {
   const int64_t nm = 2 * (int64_t)a.ndm_total;
   hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)((nm + 255) / 256)), dim3(256), 0, s,
                      reinterpret_cast<unsigned long long*>(a.ws + a.moments_off), nm);
+  if (a.dered_shift) {
+    int64_t nb = 0;
+    for (int r = 0; r < a.nranges; ++r)
+      nb = std::max<int64_t>(nb, (a.r[r].n_owned + a.w_max - 1 + (1 << a.dered_shift) - 1) >>
+                                     a.dered_shift);
+    if (nb > a.dered_nb) return hipErrorInvalidValue;
+    const dim3 gr((unsigned)a.ndm_total, (unsigned)std::max<int64_t>(1, std::min<int64_t>(
+                                             (nb + 15) / 16, 65535)));
+    const int ne = a.dered_elems;
+    if (ne <= 4)
+      hipLaunchKernelGGL(k_dered_base<4>, gr, dim3(256), 0, s, a);
+    else if (ne <= 8)
+      hipLaunchKernelGGL(k_dered_base<8>, gr, dim3(256), 0, s, a);
+    else if (ne <= 12)
+      hipLaunchKernelGGL(k_dered_base<12>, gr, dim3(256), 0, s, a);
+    else if (ne <= 16)
+      hipLaunchKernelGGL(k_dered_base<16>, gr, dim3(256), 0, s, a);
+    else if (ne <= 24)
+      hipLaunchKernelGGL(k_dered_base<24>, gr, dim3(256), 0, s, a);
+    else if (ne <= 32)
+      hipLaunchKernelGGL(k_dered_base<32>, gr, dim3(256), 0, s, a);
+    else if (ne <= 48)
+      hipLaunchKernelGGL(k_dered_base<48>, gr, dim3(256), 0, s, a);
+    else if (ne <= 64)
+      hipLaunchKernelGGL(k_dered_base<64>, gr, dim3(256), 0, s, a);
+    else
+      return hipErrorInvalidValue;
+  }
   const int32_t halo = (a.w_max - 1 + 15) & ~15;
   bool seg_ok = a.nwidths > 0 && a.cand_block % kSeg == 0 && halo <= kSegHaloMax;
   int64_t max_owned = 0;
@@ -756,10 +875,18 @@ hipError_t launch_search(const SearchArgs& a, hipStream_t s) {
     const unsigned gy =
         (unsigned)std::max<int64_t>(1, std::min<int64_t>((nseg + per_wg - 1) / per_wg, 65535));
     const size_t lds = (size_t)(kSeg + halo + 4) * sizeof(uint32_t);
-    if (a.max_boxcar < ((int64_t)1 << 28))
-      hipLaunchKernelGGL(k_seg<true>, dim3((unsigned)a.ndm_total, gy), dim3(64), lds, s, a);
-    else
-      hipLaunchKernelGGL(k_seg<false>, dim3((unsigned)a.ndm_total, gy), dim3(64), lds, s, a);
+    const dim3 gr((unsigned)a.ndm_total, gy);
+    const bool narrow = a.max_boxcar < ((int64_t)1 << 28);
+    if (a.dered_shift) {
+      if (narrow)
+        hipLaunchKernelGGL((k_seg<true, true>), gr, dim3(64), lds, s, a);
+      else
+        hipLaunchKernelGGL((k_seg<false, true>), gr, dim3(64), lds, s, a);
+    } else if (narrow) {
+      hipLaunchKernelGGL((k_seg<true, false>), gr, dim3(64), lds, s, a);
+    } else {
+      hipLaunchKernelGGL((k_seg<false, false>), gr, dim3(64), lds, s, a);
+    }
   } else {
     const unsigned gy =
         (unsigned)(a.max_cells < 1 ? 1 : (a.max_cells > 65535 ? 65535 : a.max_cells));

@@ -204,6 +204,12 @@ sdd_status plan_geometry(const sdd_plan* p, int64_t nsamp_in, CallGeom* out) {
     ws.rowcnt_off = take((int64_t)p->ndm_total * 4);
     ws.rowoff_off = take(((int64_t)p->ndm_total + 1) * 4);
     ws.robust_off = take((int64_t)p->ndm_total * 48);
+    if (p->dered_block > 0) {
+      for (size_t r = 0; r < p->ranges.size(); ++r)
+        ws.dered_nb = std::max<int64_t>(ws.dered_nb,
+                                        (g.plane_cols[r] + p->dered_block - 1) / p->dered_block);
+      ws.dered_off = take((int64_t)p->ndm_total * ws.dered_nb * 4);
+    }
   }
   ws.total = off;
   for (size_t r = 0; r < p->ranges.size(); ++r) {
@@ -467,6 +473,31 @@ extern "C" sdd_status sdd_plan_set_stats(sdd_plan* p, int32_t mode, double k, in
     p->clip_k = k;
     p->clip_iters = iters;
   }
+  p->version++;  // cached batch graphs hold the old search arguments
+  return SDD_OK;
+}
+
+extern "C" sdd_status sdd_plan_set_dereddening(sdd_plan* p, int32_t block, int32_t half) {
+  clear_error();
+  if (!p) SDD_FAIL(SDD_EINVAL, "null plan");
+  if (block == 0) {
+    p->dered_block = p->dered_half = 0;
+    p->version++;
+    return SDD_OK;
+  }
+  if (p->widths.empty()) SDD_FAIL(SDD_EINVAL, "de-reddening needs a plan with boxcar widths");
+  if (block < 64 || block > 4096 || (block & (block - 1)) != 0)
+    SDD_FAIL(SDD_EINVAL, "block %d is not a power of two in 64..4096", block);
+  if (half < 1 || (int64_t)(2 * half + 1) * block > 4096)
+    SDD_FAIL(SDD_EINVAL, "window (2*%d+1)*%d must hold 1..4096 samples with half >= 1", half,
+             block);
+  if ((int64_t)(2 * half + 1) * block <= 2 * (int64_t)p->w_max)
+    SDD_FAIL(SDD_EINVAL, "window (2*%d+1)*%d must exceed twice the widest boxcar (%d)", half,
+             block, p->w_max);
+  if ((int64_t)p->nchan * 255 * p->dec_max >= ((int64_t)1 << 30))
+    SDD_FAIL(SDD_ERANGE, "full scale nchan*255*dec_max exceeds 2^30");
+  p->dered_block = block;
+  p->dered_half = half;
   p->version++;  // cached batch graphs hold the old search arguments
   return SDD_OK;
 }

@@ -78,6 +78,8 @@ struct WsLayout {
   int64_t rowcnt_off = 0;    // [ndm_total] i32
   int64_t rowoff_off = 0;    // [ndm_total + 1] i32
   int64_t robust_off = 0;    // [ndm_total] {f64 mu, f64 sigma, u64 cnt, s1, s2, pad}
+  int64_t dered_off = 0;     // [ndm_total][dered_nb] u32 (de-reddening only)
+  int64_t dered_nb = 0;
   int64_t search_cells = 0;  // sum_r ndm_r * ncells_r
   int64_t total = 0;         // bytes without library planes
   int64_t total_planes = 0;  // bytes with library planes
@@ -107,6 +109,9 @@ struct sdd_plan {
   int32_t stats_mode = 0;
   double clip_k = 3.0;
   int32_t clip_iters = 3;
+  // running-median de-reddening of the searched series (sdd_plan_set_dereddening)
+  int32_t dered_block = 0;  // D (0: off)
+  int32_t dered_half = 0;   // h
 
   uint64_t id = 0;       // process-unique, never reused
   uint64_t version = 0;  // bumped whenever the tile choice changes
@@ -189,7 +194,7 @@ struct SearchRange {
   int32_t ndm;
   int32_t dm_offset;   // global trial index of row 0
   int32_t ncells;
-  int32_t pad;
+  int32_t full_scale;  // M = nchan * 255 * dec, bound of every plane sample
   int64_t cell_base;   // global cell index of (row 0, cell 0)
 };
 struct SearchArgs {
@@ -209,6 +214,11 @@ struct SearchArgs {
   int32_t clip_iters;
   double clip_k;
   int64_t robust_off;
+  int32_t dered_shift;   // log2 of the de-reddening block D; 0: off
+  int32_t dered_half;    // h: the median window is blocks k-h..k+h
+  int32_t dered_elems;   // samples per lane of k_dered_base's window (template)
+  int32_t dered_nb;      // baselines per trial in the workspace
+  int64_t dered_off;     // [ndm_total][dered_nb] u32 block baselines
   uint8_t* ws;           // workspace base
   int64_t cellres_off, moments_off, cellbest_off, rowcnt_off, rowoff_off;
   sdd_dm_best* best;

@@ -143,6 +143,13 @@ class Plan:
         A.check(A.lib().sdd_plan_set_stats(self._p, m, float(k), int(iters)),
                 "sdd_plan_set_stats")
 
+    def set_dereddening(self, block: int = 0, half: int = 0) -> None:
+        """Running-median de-reddening of the searched series: each block of
+        `block` samples has the lower median of blocks k-half..k+half
+        subtracted (re-centred at half the full scale). block=0 turns it off."""
+        A.check(A.lib().sdd_plan_set_dereddening(self._p, int(block), int(half)),
+                "sdd_plan_set_dereddening")
+
     def delays(self, r: int = 0) -> np.ndarray:
         out = np.empty((self.ndm[r], self.nchan), dtype=np.int32)
         A.check(A.lib().sdd_plan_delays(self._p, r, out.ctypes.data_as(C.POINTER(C.c_int32))),

@@ -239,3 +239,32 @@ def test_set_stats_validates():
     p.set_stats("clip", 2.5, 4)
     p.set_stats("mad")
     p.set_stats()
+
+
+def test_set_dereddening_validates_and_grows_the_workspace():
+    L = A.lib()
+    p = sdd.Plan([500.0, 300.0], 1e-3, dm_list=[0.0, 5.0], widths=[1, 2, 64])
+    w0 = p.geometry(20000)["workspace_bytes"]
+    # blocks outside the powers of two in 64..4096, half < 1, a window above
+    # 4096 samples; (64, 1) is a 192-sample window, above twice the widest
+    # boxcar (128)
+    for block, half in [(32, 2), (100, 1), (8192, 1), (64, 0), (1024, 2), (64, 1)]:
+        rc = L.sdd_plan_set_dereddening(p.handle, block, half)
+        if (block, half) == (64, 1):
+            assert rc == A.SDD_OK
+        else:
+            assert rc == A.SDD_EINVAL, (block, half)
+    assert L.sdd_plan_set_dereddening(p.handle, 64, 1) == A.SDD_OK
+    q = sdd.Plan([500.0, 300.0], 1e-3, dm_list=[0.0], widths=[1, 128])
+    assert L.sdd_plan_set_dereddening(q.handle, 64, 1) == A.SDD_EINVAL  # 192 <= 2 * 128
+    assert L.sdd_plan_set_dereddening(q.handle, 64, 2) == A.SDD_OK      # 320 > 2 * 128
+    q.set_dereddening(128, 1)
+    assert L.sdd_plan_set_dereddening(None, 64, 1) == A.SDD_EINVAL
+    nw = sdd.Plan([500.0, 300.0], 1e-3, dm_list=[0.0])
+    assert L.sdd_plan_set_dereddening(nw.handle, 64, 1) == A.SDD_EINVAL
+    p.set_dereddening(256, 2)
+    g = p.geometry(20000)
+    cols = max(g["plane_cols"])
+    assert g["workspace_bytes"] >= w0 + 2 * ((cols + 255) // 256) * 4
+    p.set_dereddening(0)
+    assert p.geometry(20000)["workspace_bytes"] == w0
