@@ -25,12 +25,16 @@ It follows, in order:
   * Section 2.1, after the search: removal of redundant candidates of one
     event with square stencils in the DM-time plane, then clustering of the
     candidates in the DM-time plane keeping the highest-S/N one per cluster
-    (oracle.sift).
+    (oracle.sift);
+  * Section 3.3: de-reddening of the searched series by running-median
+    subtraction (oracle.robust);
+  * Section 3.5: the folding transform (FFA) of a series at a base period
+    and the boxcar search of the folded profiles (oracle.ffa).
 
 The paper fixes no rounding, reference frequency, S/N normalisation, boxcar
 index, candidate definition, stencil size or clustering parameter; the
 readings used here are listed in the module docstrings of oracle.dedisp,
-oracle.rfi, oracle.robust and oracle.sift.
+oracle.rfi, oracle.robust, oracle.sift and oracle.ffa.
 """
 from .dedisp import *  # noqa: F401,F403
 from .dedisp import __all__ as _dedisp_all
@@ -40,5 +44,8 @@ from .robust import *  # noqa: F401,F403
 from .robust import __all__ as _robust_all
 from .sift import *  # noqa: F401,F403
 from .sift import __all__ as _sift_all
+from .ffa import *  # noqa: F401,F403
+from .ffa import __all__ as _ffa_all
 
-__all__ = list(_dedisp_all) + list(_rfi_all) + list(_robust_all) + list(_sift_all)
+__all__ = (list(_dedisp_all) + list(_rfi_all) + list(_robust_all) + list(_sift_all)
+           + list(_ffa_all))
