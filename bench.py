@@ -192,6 +192,56 @@ def robust_bench(sdd, torch, plan, xt, planes, out, ws, reps: int = 3):
     return res
 
 
+def ffa_levels(m: int, p: int):
+    """(LDS sub-stack depth d0, HBM passes) of the library's FFA schedule:
+    the shallowest depth whose sub-stacks hold <= 256 rows and <= 8192 bins."""
+    fl = 0
+    while (2 << fl) <= m:
+        fl += 1
+    d0 = 0
+    while d0 < fl and (((m + (1 << d0) - 1) >> d0) * p > 8192 or ((m + (1 << d0) - 1) >> d0) > 256):
+        d0 += 1
+    return d0
+
+
+def ffa_bench(sdd, torch, plane, n_owned: int, reps: int = 3):
+    """FFA folding + boxcar search of every trial of the step's plane (2048
+    series of 2^18 samples) at base periods of 1024 and 128 samples.
+    Algorithmic HBM bytes per folded sample: 4 (moments) + 4 + 4 (LDS levels:
+    read the rows, write the sub-stack profiles) + 12 per HBM pass (two
+    reads, one write) + 4 (boxcar read)."""
+    import ctypes as C
+    from paper_2605_03531_amd import _capi as A
+    L = A.lib()
+    series = plane[:, :n_owned]
+    res = {}
+    for p in (1024, 128):
+        m = n_owned // p
+        nb = C.c_int64()
+        A.check(L.sdd_ffa_workspace_size(series.shape[0], n_owned, p, C.byref(nb)), "ws")
+        ws = torch.empty(nb.value, dtype=torch.uint8, device=plane.device)
+        out = sdd.ffa_search(series, p, [1, 2, 4, 8, 16, 32, 64], 4096 * 255, workspace=ws)
+        torch.cuda.synchronize()
+        A.check(L.sdd_profile_enable(1), "profile")
+        for _ in range(reps):
+            sdd.ffa_search(series, p, [1, 2, 4, 8, 16, 32, 64], 4096 * 255, workspace=ws, out=out)
+        torch.cuda.synchronize()
+        ms, n = C.c_double(), C.c_int64()
+        A.check(L.sdd_profile_read(A.STAGES["ffa"], C.byref(ms), C.byref(n)), "read")
+        L.sdd_profile_enable(0)
+        t = ms.value / max(n.value, 1)
+        d0 = ffa_levels(m, p)
+        nel = series.shape[0] * m * p
+        by = nel * (16 + 12 * d0)
+        best, _, _ = out.host()
+        res[f"period_{p}"] = {"m": m, "hbm_passes": d0, "ms": round(t, 4),
+                              "gsamples_per_s": round(nel / t / 1e6, 1),
+                              "algorithmic_bytes": by, "gbps": round(by / t / 1e6, 1),
+                              "max_snr": round(float(best["snr"].max()), 2)}
+        del ws
+    return res
+
+
 def serve_bench(sdd, torch, nbeams: int, sat_chunks: int, rt_periods: int, max_batch: int,
                 nstreams: int, per_item: bool = True):
     """Streaming server with nbeams beams (1024/2048/4096 channels by beam
@@ -438,6 +488,8 @@ def main() -> int:
     log(f"rfi: {res['rfi']}")
     res["robust_stats"] = robust_bench(sdd, torch, plan, xt, planes, out, ws)
     log(f"robust statistics: {res['robust_stats']}")
+    res["ffa"] = ffa_bench(sdd, torch, planes[0], n_owned)
+    log(f"ffa: {res['ffa']}")
     if args.copy_calibration:
         src = torch.empty(1 << 30, dtype=torch.uint8, device=dev).fill_(7)
         dst = torch.empty_like(src)

@@ -500,11 +500,63 @@ sdd_status sdd_sift_candidates(const sdd_plan* plan, const sdd_candidate* d_cand
                                sdd_candidate* d_out, int32_t* d_nout, int32_t* d_sizes,
                                void* d_workspace, int64_t ws_bytes, void* stream);
 
+/* ---- FFA folding and the boxcar search of folded profiles ---------------- */
+
+/* Section 3.5: a series of N samples is stacked as m = floor(N / period)
+ * rows of `period` samples (samples past m * period are not folded) and the
+ * Fast Folding Algorithm (Staelin 1969) turns the stack into m folded
+ * profiles. Profile s drifts s bins over the m - 1 row steps, i.e. it folds
+ * at the trial frequency f_s = (1/p - s/((m-1) p^2)) / tau0 and period
+ * p_s = p^2 / (p - s/(m-1)) * tau0 of Section 3.5 (p = period, tau0 the
+ * sampling interval). Recursion: a stack of len > 1 rows splits into
+ * h = len/2 head and t = len - h tail rows; its profile s is head profile
+ * k_h plus tail profile k_t rolled left by s - k_t bins, with
+ * k_h = round(s(h-1)/(len-1)), k_t = round(s(t-1)/(len-1)), round(x) =
+ * floor(x + 1/2) (for m a power of two: the classic FFA, k_h = k_t = s/2).
+ * Each profile is searched with circular boxcars of the given widths:
+ * B_w[j] = sum of bins j .. j+w-1 (mod period), S/N = (B - w m mu) /
+ * (sigma sqrt(m w)) with mu, sigma the mean and population deviation of the
+ * m * period folded samples (exact integer moments, FP64); the best is the
+ * largest S/N, then the smaller bin, then the smaller width; sigma = 0 gives
+ * (0, 0, widths[0]). Profile bins are exact uint32 sums. */
+#define SDD_FFA_MAX_PERIOD 4096
+
+typedef struct sdd_ffa_best {  /* best boxcar of one folded profile */
+  float snr;
+  int32_t bin;    /* first bin of the boxcar */
+  int32_t width;
+  int32_t pad;
+} sdd_ffa_best;
+
+/* Device scratch for sdd_ffa_search: two uint32 stacks of nseries * m *
+ * period plus the moments. */
+sdd_status sdd_ffa_workspace_size(int32_t nseries, int64_t nsamp, int32_t period, int64_t* bytes);
+
+/* Folds and searches nseries series (device, uint32; series k at
+ * d_series + k * pitch elements, nsamp samples each, e.g. the rows of a
+ * DM-time plane) at one base period on device `device`.
+ *   max_value   a bound of every sample (a plane's nchan * 255 * dec); the
+ *               call is refused (ERANGE) when m * max_value >= 2^32, so
+ *               every profile bin is exact in 32 bits;
+ *   widths      host, nwidths (1..SDD_MAX_WIDTHS) strictly increasing
+ *               widths within 1 .. period-1;
+ *   d_profiles  device uint32 [nseries][m][period] or NULL (not stored);
+ *   d_best      device [nseries][m] best boxcar per profile;
+ *   d_stats     device [nseries] moments of the folded samples, or NULL.
+ * Enqueued on stream; nothing returns to the host. EINVAL on null buffers,
+ * period outside 2..SDD_FFA_MAX_PERIOD, nsamp < period, pitch < nsamp or
+ * bad widths; ENOMEM when ws_bytes is too small. */
+sdd_status sdd_ffa_search(int32_t device, const uint32_t* d_series, int64_t pitch,
+                          int32_t nseries, int64_t nsamp, int32_t period, uint32_t max_value,
+                          const int32_t* widths, int32_t nwidths, uint32_t* d_profiles,
+                          sdd_ffa_best* d_best, sdd_dm_stats* d_stats, void* d_ws,
+                          int64_t ws_bytes, void* stream);
+
 /* ---- kernel timing (benchmarks) ----------------------------------------- */
 
 /* Stages whose kernels can be timed. */
 enum { SDD_STAGE_CORNER_TURN = 0, SDD_STAGE_DECIMATE = 1, SDD_STAGE_DEDISPERSE = 2,
-       SDD_STAGE_SEARCH = 3, SDD_STAGE_SIFT = 4, SDD_NSTAGES = 5 };
+       SDD_STAGE_SEARCH = 3, SDD_STAGE_SIFT = 4, SDD_STAGE_FFA = 5, SDD_NSTAGES = 6 };
 
 /* on != 0: from now on every stage launch is bracketed by two HIP events
  * recorded on the launch stream; the accumulated times are reset. on == 0:

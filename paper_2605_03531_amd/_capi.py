@@ -151,10 +151,13 @@ _PROTOS = {
     "sdd_sift_workspace_size": (i32, [i32, C.POINTER(i64)]),
     "sdd_sift_candidates": (i32, [vp, vp, vp, i32, C.POINTER(SiftDesc), vp, vp, vp, vp, i64,
                                   vp]),
+    "sdd_ffa_workspace_size": (i32, [i32, i64, i32, C.POINTER(i64)]),
+    "sdd_ffa_search": (i32, [i32, vp, i64, i32, i64, i32, C.c_uint32, C.POINTER(i32), i32, vp, vp,
+                             vp, vp, i64, vp]),
     "sdd_profile_enable": (i32, [i32]),
     "sdd_profile_read": (i32, [i32, C.POINTER(f64), C.POINTER(i64)]),
 }
-STAGES = {"corner_turn": 0, "decimate": 1, "dedisperse": 2, "search": 3, "sift": 4}
+STAGES = {"corner_turn": 0, "decimate": 1, "dedisperse": 2, "search": 3, "sift": 4, "ffa": 5}
 
 _lib = None
 

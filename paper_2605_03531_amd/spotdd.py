@@ -16,6 +16,7 @@ CAND_DTYPE = np.dtype([("range", "<i4"), ("dm_index", "<i4"), ("sample", "<i8"),
 BEST_DTYPE = np.dtype([("snr", "<f4"), ("width", "<i4"), ("sample", "<i8")])
 STATS_DTYPE = np.dtype([("n", "<i8"), ("s1", "<u8"), ("s2", "<u8"), ("mean", "<f8"),
                         ("std", "<f8")])
+FFA_BEST_DTYPE = np.dtype([("snr", "<f4"), ("bin", "<i4"), ("width", "<i4"), ("pad", "<i4")])
 assert CAND_DTYPE.itemsize == C.sizeof(A.Candidate)
 assert BEST_DTYPE.itemsize == C.sizeof(A.DmBest)
 assert STATS_DTYPE.itemsize == C.sizeof(A.DmStats)
@@ -371,6 +372,58 @@ class SiftOut:
         n = int(self.n.cpu()[0])
         raw = self.cands[: n * CAND_DTYPE.itemsize].cpu().numpy().tobytes()
         return np.frombuffer(raw, dtype=CAND_DTYPE), self.sizes[:n].cpu().numpy()
+
+
+@dataclass
+class FfaOut:
+    best: "object"      # device uint8 tensor holding sdd_ffa_best[nseries * m]
+    profiles: "object"  # device int32 tensor [nseries][m][period] (uint32 bits) or None
+    stats: "object"     # device uint8 tensor holding sdd_dm_stats[nseries] or None
+    m: int
+
+    def host(self):
+        """(best [nseries][m] structured, profiles uint32 or None, stats or None)."""
+        best = np.frombuffer(self.best.cpu().numpy().tobytes(), dtype=FFA_BEST_DTYPE)
+        best = best.reshape(-1, self.m)
+        prof = None if self.profiles is None else self.profiles.cpu().numpy().view(np.uint32)
+        st = None if self.stats is None else np.frombuffer(self.stats.cpu().numpy().tobytes(),
+                                                           dtype=STATS_DTYPE)
+        return best, prof, st
+
+
+def ffa_search(series, period: int, widths: Sequence[int], max_value: int, profiles: bool = False,
+               stats: bool = True, workspace=None, stream=None, out: "FfaOut" = None) -> FfaOut:
+    """FFA folding and boxcar search (sdd_ffa_search) of the rows of a 2-D
+    device int32/uint32-bits tensor (e.g. a DM-time plane; rows may be a
+    strided view with unit column stride): every row of `nsamp` columns is
+    folded at the base period into m = nsamp // period profiles."""
+    torch = _torch()
+    if series.dim() != 2 or series.stride(1) != 1 or series.element_size() != 4:
+        raise ValueError("series must be a 2-D 32-bit device tensor with unit column stride")
+    ns, nsamp = series.shape
+    m = nsamp // period
+    dev = series.device
+    w = (C.c_int32 * len(widths))(*[int(v) for v in widths])
+    if out is None:
+        out = FfaOut(torch.empty(ns * m * FFA_BEST_DTYPE.itemsize, dtype=torch.uint8, device=dev),
+                     torch.empty((ns, m, period), dtype=torch.int32, device=dev) if profiles
+                     else None,
+                     torch.empty(ns * STATS_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+                     if stats else None, m)
+    if workspace is None:
+        nb = C.c_int64()
+        A.check(A.lib().sdd_ffa_workspace_size(ns, nsamp, int(period), C.byref(nb)),
+                "sdd_ffa_workspace_size")
+        workspace = torch.empty(nb.value, dtype=torch.uint8, device=dev)
+    A.check(A.lib().sdd_ffa_search(dev.index or 0, series.data_ptr(), series.stride(0), ns, nsamp,
+                                   int(period), int(max_value), w, len(widths),
+                                   out.profiles.data_ptr() if out.profiles is not None else None,
+                                   out.best.data_ptr(),
+                                   out.stats.data_ptr() if out.stats is not None else None,
+                                   workspace.data_ptr(), workspace.numel(),
+                                   _stream_handle(stream, dev.index or 0)),
+            "sdd_ffa_search")
+    return out
 
 
 def plane_host(plane, cols: int) -> np.ndarray:
