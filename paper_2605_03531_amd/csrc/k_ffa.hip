@@ -14,8 +14,8 @@
 //   k_ffa_lds      the lowest levels: one workgroup per sub-stack that fits
 //                  in LDS (ping-pong), from the input rows to its profiles
 //   k_ffa_pass     one upper level through HBM: out[i] = A[a] + roll(A[b], sh)
-//   k_ffa_boxcar   per profile: circular uint64 prefix sums in LDS, each
-//                  width's largest sum and first bin, FP64 S/N, the best.
+//   k_ffa_boxcar   one wavefront per profile: circular uint64 prefix sums in
+//                  LDS, each width's largest sum and first bin, FP64 S/N.
 // Profiles are uint32 (the host checks m * max_value < 2^32), boxcar sums
 // uint64: every sum is exact and every choice has a total order.
 #include <algorithm>
@@ -162,7 +162,20 @@ __global__ __launch_bounds__(kThreads) void k_ffa_lds(FfaArgs a, int d0, int32_t
   uint32_t* A = sm;
   uint32_t* B = sm + cap;
   const int32_t ne = len * p;
-  for (int32_t e = threadIdx.x; e < ne; e += kThreads) A[e] = src[e];
+  // 8 loads in flight per thread before their LDS stores
+  for (int32_t e0 = 0; e0 < ne; e0 += 8 * kThreads) {
+    uint32_t v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int32_t e = e0 + u * kThreads + (int32_t)threadIdx.x;
+      v[u] = e < ne ? src[e] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int32_t e = e0 + u * kThreads + (int32_t)threadIdx.x;
+      if (e < ne) A[e] = v[u];
+    }
+  }
   int depth = 0;  // levels of the sub-stack: ceil(log2 len)
   while ((1 << depth) < len) ++depth;
   const RowLane L = row_lane(p);
@@ -215,6 +228,7 @@ __global__ __launch_bounds__(kThreads) void k_ffa_pass(FfaArgs a, int d, const u
     for (int32_t j = L.j0; j < p; j += L.jstep) po[j] = pa[j];
   } else {
     const uint32_t* pb = s + (int64_t)rb * p;
+#pragma unroll 4
     for (int32_t j = L.j0; j < p; j += L.jstep) {
       int32_t k = j + sh;
       if (k >= p) k -= p;
@@ -229,117 +243,103 @@ __device__ inline bool bj_better(unsigned long long b, int32_t j, unsigned long 
   return b > b2 || (b == b2 && j < j2);
 }
 
-// Best (S/N, bin, width) of profile blockIdx.x of series blockIdx.y.
+// mu = S1/n, sigma = sqrt(n S2 - S1^2)/n with the numerator exact (128-bit).
+__device__ inline void fold_mean_sigma(uint64_t n, uint64_t s1, uint64_t s2, double* mu,
+                                       double* sigma) {
+  const uint64_t p_lo = n * s2, p_hi = __umul64hi(n, s2);
+  const uint64_t q_lo = s1 * s1, q_hi = __umul64hi(s1, s1);
+  const uint64_t d_lo = p_lo - q_lo;
+  const uint64_t d_hi = p_hi - q_hi - (p_lo < q_lo ? 1ull : 0ull);
+  *mu = (double)s1 / (double)n;
+  *sigma = 0.0;
+  if (d_hi != 0 || d_lo != 0)
+    *sigma = sqrt((double)d_hi * 18446744073709551616.0 + (double)d_lo) / (double)n;
+}
+
+// Best (S/N, bin, width) of folded profiles: one wavefront per profile
+// (profile 4 * blockIdx.x + wave of series blockIdx.y). Lane l sums its
+// chunk of ceil(p / 64) consecutive bins; a wave scan of the chunk sums gives
+// P[k] = sum of bins < k in LDS (P[p] the total), and the circular boxcar
+// from bin j is P[j + w] - P[j], or P[p] - P[j] + P[j + w - p] past the end.
+// Per width the largest sum and its first bin (wave reduction), then FP64
+// S/N, compared in the F6 order as the widths go.
 __global__ __launch_bounds__(kThreads) void k_ffa_boxcar(FfaArgs a, const uint32_t* prof,
                                                          int64_t prof_pitch) {
-  extern __shared__ unsigned long long P[];  // p + w_max entries
-  __shared__ unsigned long long rb[kThreads / 64];
-  __shared__ int32_t rj[kThreads / 64];
-  __shared__ unsigned long long wb[SDD_MAX_WIDTHS];
-  __shared__ int32_t wj[SDD_MAX_WIDTHS];
-  __shared__ unsigned long long scan[kThreads / 64];
-  const int32_t s = blockIdx.x, sr = blockIdx.y, p = a.p;
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  extern __shared__ unsigned long long P_all[];  // 4 x (p + 1)
+  const int32_t p = a.p, sr = blockIdx.y;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int32_t s = (int32_t)blockIdx.x * (kThreads / 64) + wid;
+  if (s >= a.m) return;  // whole wavefront: no workgroup barrier below
+  unsigned long long* P = P_all + (int64_t)wid * (p + 1);
   const uint32_t* row = prof + (int64_t)sr * prof_pitch + (int64_t)s * p;
-  const int32_t wmax = a.widths[a.nwidths - 1];
-  const int32_t L = p + wmax - 1;  // circularly extended profile
-  // P[k] = sum of the first k extended bins: per-thread chunk sums, a
-  // workgroup scan of the chunk totals, then the chunk prefixes
-  const int32_t per = (L + kThreads - 1) / kThreads;
-  const int32_t k0 = min(tid * per, L), k1 = min(k0 + per, L);
+  const int32_t c = (p + 63) / 64;
+  const int32_t k0 = min(lane * c, p), k1 = min(k0 + c, p);
   unsigned long long part = 0;
-  for (int32_t k = k0; k < k1; ++k) part += row[k < p ? k : k - p];
+#pragma unroll 4
+  for (int32_t k = k0; k < k1; ++k) part += row[k];
   unsigned long long inc = part;
   for (int o = 1; o < 64; o <<= 1) {
     const unsigned long long t = __shfl_up(inc, o, 64);
     if (lane >= o) inc += t;
   }
-  if (lane == 63) scan[wid] = inc;
-  __syncthreads();
   unsigned long long off = inc - part;
-  for (int w = 0; w < wid; ++w) off += scan[w];
   for (int32_t k = k0; k < k1; ++k) {
     P[k] = off;
-    off += row[k < p ? k : k - p];
+    off += row[k];
   }
-  if (k1 == L && k0 < k1) P[L] = off;
-  __syncthreads();
-  for (int q = 0; q < a.nwidths; ++q) {
-    const int32_t w = a.widths[q];
-    unsigned long long bb = 0ull;
-    int32_t bjj = 0x7fffffff;
-    for (int32_t j = tid; j < p; j += kThreads) {
-      const unsigned long long b = P[j + w] - P[j];
-      if (bj_better(b, j, bb, bjj)) {
-        bb = b;
-        bjj = j;
-      }
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-      const unsigned long long b2 = __shfl_xor(bb, o, 64);
-      const int32_t j2 = __shfl_xor(bjj, o, 64);
-      if (bj_better(b2, j2, bb, bjj)) {
-        bb = b2;
-        bjj = j2;
-      }
-    }
-    if (lane == 0) {
-      rb[wid] = bb;
-      rj[wid] = bjj;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      unsigned long long b = rb[0];
-      int32_t j = rj[0];
-      for (int k = 1; k < kThreads / 64; ++k)
-        if (bj_better(rb[k], rj[k], b, j)) {
-          b = rb[k];
-          j = rj[k];
+  const unsigned long long total = __shfl(inc, 63, 64);
+  if (lane == 0) P[p] = total;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const uint64_t n = (uint64_t)a.m * (uint64_t)p;
+  double mu, sigma;
+  fold_mean_sigma(n, a.moments[2 * sr], a.moments[2 * sr + 1], &mu, &sigma);
+  double bs = 0.0;
+  int32_t bj = 0, bw = a.widths[0];
+  if (sigma > 0.0) {
+    bs = -INFINITY;
+    for (int q = 0; q < a.nwidths; ++q) {
+      const int32_t w = a.widths[q];
+      unsigned long long bb = 0ull;
+      int32_t bjj = 0x7fffffff;
+      for (int32_t j = lane; j < p; j += 64) {
+        const int32_t e = j + w;
+        const unsigned long long b = e <= p ? P[e] - P[j] : total - P[j] + P[e - p];
+        if (bj_better(b, j, bb, bjj)) {
+          bb = b;
+          bjj = j;
         }
-      wb[q] = b;
-      wj[q] = j;
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long b2 = __shfl_xor(bb, o, 64);
+        const int32_t j2 = __shfl_xor(bjj, o, 64);
+        if (bj_better(b2, j2, bb, bjj)) {
+          bb = b2;
+          bjj = j2;
+        }
+      }
+      const double sn =
+          ((double)bb - (double)w * (double)a.m * mu) / (sigma * sqrt((double)a.m * (double)w));
+      if (sn > bs || (sn == bs && bjj < bj)) {  // widths ascend: a tie keeps the smaller
+        bs = sn;
+        bj = bjj;
+        bw = w;
+      }
     }
-    __syncthreads();
   }
-  if (tid == 0) {
-    const uint64_t n = (uint64_t)a.m * (uint64_t)p;
-    const uint64_t s1 = a.moments[2 * sr], s2 = a.moments[2 * sr + 1];
-    // mu = S1/n, sigma = sqrt(n S2 - S1^2)/n with the numerator exact (128-bit)
-    const uint64_t p_lo = n * s2, p_hi = __umul64hi(n, s2);
-    const uint64_t q_lo = s1 * s1, q_hi = __umul64hi(s1, s1);
-    const uint64_t d_lo = p_lo - q_lo;
-    const uint64_t d_hi = p_hi - q_hi - (p_lo < q_lo ? 1ull : 0ull);
-    const double mu = (double)s1 / (double)n;
-    double sigma = 0.0;
-    if (d_hi != 0 || d_lo != 0)
-      sigma = sqrt((double)d_hi * 18446744073709551616.0 + (double)d_lo) / (double)n;
+  if (lane == 0) {
     sdd_ffa_best o;
-    o.snr = 0.f;
-    o.bin = 0;
-    o.width = a.widths[0];
+    o.snr = (float)bs;
+    o.bin = bj;
+    o.width = bw;
     o.pad = 0;
-    if (sigma > 0.0) {
-      double bs = -INFINITY;
-      int32_t bj = 0, bw = 0;
-      for (int q = 0; q < a.nwidths; ++q) {
-        const double w = (double)a.widths[q];
-        const double sn = ((double)wb[q] - w * (double)a.m * mu) / (sigma * sqrt((double)a.m * w));
-        if (sn > bs || (sn == bs && (wj[q] < bj || (wj[q] == bj && a.widths[q] < bw)))) {
-          bs = sn;
-          bj = wj[q];
-          bw = a.widths[q];
-        }
-      }
-      o.snr = (float)bs;
-      o.bin = bj;
-      o.width = bw;
-    }
     a.best[(int64_t)sr * a.m + s] = o;
     if (s == 0 && a.stats) {
       sdd_dm_stats st;
       st.n = (int64_t)n;
-      st.s1 = s1;
-      st.s2 = s2;
+      st.s1 = a.moments[2 * sr];
+      st.s2 = a.moments[2 * sr + 1];
       st.mean = mu;
       st.std = sigma;
       a.stats[sr] = st;
@@ -455,13 +455,12 @@ extern "C" sdd_status sdd_ffa_search(int32_t device, const uint32_t* d_series, i
   uint32_t* cur = dst_of(0, nlev);
   const int32_t cap = (int32_t)(height(d0) * period);
   const size_t lds_a = 2 * (size_t)cap * sizeof(uint32_t);
-  const size_t lds_b = (size_t)(period + widths[nwidths - 1]) * sizeof(unsigned long long);
-  // both stay within 64 KiB (cap <= 8192; period + w_max <= 8191), and gfx950
-  // gives a workgroup up to 160 KiB, static arrays included
+  const size_t lds_b = (size_t)(kThreads / 64) * (period + 1) * sizeof(unsigned long long);
+  // at most 64 KiB and 4 x 4097 x 8 bytes: within gfx950's 160 KiB per workgroup
   SDD_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ffa_lds),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 65536));
   SDD_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ffa_boxcar),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, 65536));
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_b));
   hipLaunchKernelGGL(k_ffa_lds, dim3(1u << d0, (unsigned)nseries), dim3(kThreads), lds_a, s, a,
                      d0, cap, cur, stack);
   const int32_t rstep = period >= kThreads ? 1 : kThreads / period;
@@ -471,8 +470,8 @@ extern "C" sdd_status sdd_ffa_search(int32_t device, const uint32_t* d_series, i
                        dim3(kThreads), 0, s, a, d0 - k, cur, stack, nxt, stack);
     cur = nxt;
   }
-  hipLaunchKernelGGL(k_ffa_boxcar, dim3((unsigned)m, (unsigned)nseries), dim3(kThreads), lds_b, s,
-                     a, cur, stack);
+  hipLaunchKernelGGL(k_ffa_boxcar, dim3((unsigned)((m + 3) / 4), (unsigned)nseries),
+                     dim3(kThreads), lds_b, s, a, cur, stack);
   SDD_HIP_TRY(hipGetLastError());
   return SDD_OK;
 }
