@@ -29,6 +29,7 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kLdsElems = 8192;  // u32 elements per LDS buffer of k_ffa_lds (two buffers)
 constexpr int kLdsRows = 256;    // rows of a sub-stack of k_ffa_lds
+constexpr int kLdsThreads = 512; // workgroup of k_ffa_lds
 
 struct FfaArgs {
   const uint32_t* in;  // series s at in + s * in_pitch
@@ -39,6 +40,7 @@ struct FfaArgs {
   int32_t nwidths;
   int32_t widths[SDD_MAX_WIDTHS];
   unsigned long long* moments;  // [nseries] {s1, s2}
+  const int4* tab;              // [depth][m] sources of every row at the HBM-pass depths
   sdd_ffa_best* best;           // [nseries][m]
   sdd_dm_stats* stats;          // [nseries] or null
 };
@@ -123,16 +125,18 @@ __global__ __launch_bounds__(kThreads) void k_ffa_moments(FfaArgs a) {
   }
 }
 
-// Thread layout over rows of p bins: p >= 256 -> one row at a time, bins
-// strided by 256; p < 256 -> R = 256 / p rows at a time, one bin each.
+// Thread layout over rows of p bins for a workgroup of T threads: p >= T ->
+// one row at a time, bins strided by T; p < T -> R = T / p rows at a time,
+// one bin each.
 struct RowLane {
   int32_t r0, j0, rstep, jstep;
   bool on;
 };
+template <int T = kThreads>
 __device__ inline RowLane row_lane(int32_t p) {
   RowLane L;
-  L.jstep = p >= kThreads ? kThreads : p;
-  L.rstep = kThreads / L.jstep;
+  L.jstep = p >= T ? T : p;
+  L.rstep = T / L.jstep;
   L.r0 = (int32_t)threadIdx.x / L.jstep;
   L.j0 = (int32_t)threadIdx.x % L.jstep;
   L.on = L.r0 < L.rstep;
@@ -142,10 +146,11 @@ __device__ inline RowLane row_lane(int32_t p) {
 // The lowest levels of one sub-stack (node `blockIdx.x` at depth d0, of at
 // most kLdsRows and kLdsElems / p rows) from the input rows to its profiles, written to
 // dst (series stride dst_pitch).
-__global__ __launch_bounds__(kThreads) void k_ffa_lds(FfaArgs a, int d0, int32_t cap,
-                                                      uint32_t* dst, int64_t dst_pitch) {
+__global__ __launch_bounds__(kLdsThreads) void k_ffa_lds(FfaArgs a, int d0, int32_t cap,
+                                                         uint32_t* dst, int64_t dst_pitch) {
   extern __shared__ uint32_t sm[];  // 2 * cap, cap >= rows of the sub-stack * p
-  __shared__ int32_t tab[3 * kLdsRows];
+  // per (level, row): a | b << 8 | copy << 16 | roll << 17 (rows < 256, roll < 4096)
+  __shared__ uint32_t tab[8 * kLdsRows];
   const int32_t sr = blockIdx.y, p = a.p;
   // node index -> rows [lo, lo + len): bit d0-1-k of the index picks head or tail
   int32_t lo = 0, len = a.m;
@@ -163,30 +168,36 @@ __global__ __launch_bounds__(kThreads) void k_ffa_lds(FfaArgs a, int d0, int32_t
   uint32_t* B = sm + cap;
   const int32_t ne = len * p;
   // 8 loads in flight per thread before their LDS stores
-  for (int32_t e0 = 0; e0 < ne; e0 += 8 * kThreads) {
+  for (int32_t e0 = 0; e0 < ne; e0 += 8 * kLdsThreads) {
     uint32_t v[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int32_t e = e0 + u * kThreads + (int32_t)threadIdx.x;
+      const int32_t e = e0 + u * kLdsThreads + (int32_t)threadIdx.x;
       v[u] = e < ne ? src[e] : 0u;
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int32_t e = e0 + u * kThreads + (int32_t)threadIdx.x;
+      const int32_t e = e0 + u * kLdsThreads + (int32_t)threadIdx.x;
       if (e < ne) A[e] = v[u];
     }
   }
-  int depth = 0;  // levels of the sub-stack: ceil(log2 len)
+  int depth = 0;  // levels of the sub-stack: ceil(log2 len) <= 8
   while ((1 << depth) < len) ++depth;
-  const RowLane L = row_lane(p);
+  for (int32_t k = threadIdx.x; k < depth * len; k += kLdsThreads) {
+    const int d = k / len;
+    const int32_t r = k - d * len;
+    int32_t ra, rb, sh;
+    ffa_sources(len, r, d, p, &ra, &rb, &sh);
+    tab[k] = (uint32_t)ra | (rb < 0 ? 1u << 16 : (uint32_t)rb << 8) | ((uint32_t)sh << 17);
+  }
+  const RowLane L = row_lane<kLdsThreads>(p);
   for (int d = depth - 1; d >= 0; --d) {
-    __syncthreads();  // A complete; previous readers of tab done
-    for (int32_t r = threadIdx.x; r < len; r += kThreads)
-      ffa_sources(len, r, d, p, &tab[3 * r], &tab[3 * r + 1], &tab[3 * r + 2]);
-    __syncthreads();
+    __syncthreads();  // A (and at the first level the table) complete
     if (L.on)
       for (int32_t r = L.r0; r < len; r += L.rstep) {
-        const int32_t ra = tab[3 * r], rb = tab[3 * r + 1], sh = tab[3 * r + 2];
+        const uint32_t t = tab[d * len + r];
+        const int32_t ra = (int32_t)(t & 255u), sh = (int32_t)(t >> 17);
+        const int32_t rb = (t >> 16) & 1u ? -1 : (int32_t)((t >> 8) & 255u);
         const uint32_t* pa = A + ra * p;
         uint32_t* po = B + r * p;
         if (rb < 0) {
@@ -206,41 +217,49 @@ __global__ __launch_bounds__(kThreads) void k_ffa_lds(FfaArgs a, int d0, int32_t
   }
   __syncthreads();
   uint32_t* out = dst + (int64_t)sr * dst_pitch + (int64_t)lo * p;
-  for (int32_t e = threadIdx.x; e < ne; e += kThreads) out[e] = A[e];
+  for (int32_t e = threadIdx.x; e < ne; e += kLdsThreads) out[e] = A[e];
+}
+
+// Sources of every row at depths 0 .. d0-1 (the HBM passes), once per call.
+__global__ __launch_bounds__(256) void k_ffa_table(int32_t m, int32_t p, int d0, int4* tab) {
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k >= (int64_t)d0 * m) return;
+  const int d = (int)(k / m);
+  const int32_t i = (int32_t)(k - (int64_t)d * m);
+  int4 t;
+  ffa_sources(m, i, d, p, &t.x, &t.y, &t.z);
+  t.w = 0;
+  tab[k] = t;
 }
 
 // One upper level (depth d) through HBM: rows of src (series stride
-// src_pitch) to rows of dst.
+// src_pitch) to rows of dst; workgroup blockIdx.x of gridDim.x walks every
+// gridDim.x-th group of rows of series blockIdx.y.
 __global__ __launch_bounds__(kThreads) void k_ffa_pass(FfaArgs a, int d, const uint32_t* src,
                                                        int64_t src_pitch, uint32_t* dst,
                                                        int64_t dst_pitch) {
   const int32_t sr = blockIdx.y, p = a.p;
   const RowLane L = row_lane(p);
   if (!L.on) return;
-  const int32_t i = (int32_t)blockIdx.x * L.rstep + L.r0;
-  if (i >= a.m) return;
-  int32_t ra, rb, sh;
-  ffa_sources(a.m, i, d, p, &ra, &rb, &sh);
   const uint32_t* s = src + (int64_t)sr * src_pitch;
-  const uint32_t* pa = s + (int64_t)ra * p;
-  uint32_t* po = dst + (int64_t)sr * dst_pitch + (int64_t)i * p;
-  if (rb < 0) {
-    for (int32_t j = L.j0; j < p; j += L.jstep) po[j] = pa[j];
-  } else {
-    const uint32_t* pb = s + (int64_t)rb * p;
+  for (int32_t i = (int32_t)blockIdx.x * L.rstep + L.r0; i < a.m;
+       i += (int32_t)gridDim.x * L.rstep) {
+    const int4 t = a.tab[(int64_t)d * a.m + i];
+    const int32_t ra = t.x, rb = t.y, sh = t.z;
+    const uint32_t* pa = s + (int64_t)ra * p;
+    uint32_t* po = dst + (int64_t)sr * dst_pitch + (int64_t)i * p;
+    if (rb < 0) {
+      for (int32_t j = L.j0; j < p; j += L.jstep) po[j] = pa[j];
+    } else {
+      const uint32_t* pb = s + (int64_t)rb * p;
 #pragma unroll 4
-    for (int32_t j = L.j0; j < p; j += L.jstep) {
-      int32_t k = j + sh;
-      if (k >= p) k -= p;
-      po[j] = pa[j] + pb[k];
+      for (int32_t j = L.j0; j < p; j += L.jstep) {
+        int32_t k = j + sh;
+        if (k >= p) k -= p;
+        po[j] = pa[j] + pb[k];
+      }
     }
   }
-}
-
-// (B, j) order of one width: the larger sum, then the smaller bin.
-__device__ inline bool bj_better(unsigned long long b, int32_t j, unsigned long long b2,
-                                 int32_t j2) {
-  return b > b2 || (b == b2 && j < j2);
 }
 
 // mu = S1/n, sigma = sqrt(n S2 - S1^2)/n with the numerator exact (128-bit).
@@ -256,93 +275,119 @@ __device__ inline void fold_mean_sigma(uint64_t n, uint64_t s1, uint64_t s2, dou
     *sigma = sqrt((double)d_hi * 18446744073709551616.0 + (double)d_lo) / (double)n;
 }
 
+// (S/N, bin, width) order of the search: the larger S/N, then the smaller
+// bin, then the smaller width.
+__device__ inline bool snr_better(double s, int32_t j, int32_t w, double s2, int32_t j2,
+                                  int32_t w2) {
+  return s > s2 || (s == s2 && (j < j2 || (j == j2 && w < w2)));
+}
+
 // Best (S/N, bin, width) of folded profiles: one wavefront per profile
-// (profile 4 * blockIdx.x + wave of series blockIdx.y). Lane l sums its
-// chunk of ceil(p / 64) consecutive bins; a wave scan of the chunk sums gives
-// P[k] = sum of bins < k in LDS (P[p] the total), and the circular boxcar
-// from bin j is P[j + w] - P[j], or P[p] - P[j] + P[j + w - p] past the end.
-// Per width the largest sum and its first bin (wave reduction), then FP64
-// S/N, compared in the F6 order as the widths go.
+// (profiles 4 * blockIdx.x + wave + 4 * gridDim.x * k of series
+// blockIdx.y). Lane l sums its chunk of ceil(p / 64) consecutive bins; a
+// wave scan of the chunk sums gives P[k] = sum of bins < k in LDS (P[p] the
+// total), and the circular boxcar from bin j is P[j + w] - P[j], or
+// P[p] - P[j] + P[j + w - p] past the end. Each lane keeps, per width, the
+// largest sum over its bins (first bin on ties: its bins ascend), turns it
+// into the FP64 S/N (B - w m mu) / (sigma sqrt(m w)) and keeps its best in
+// the search's order; one wave reduction in the same order ends the profile.
 __global__ __launch_bounds__(kThreads) void k_ffa_boxcar(FfaArgs a, const uint32_t* prof,
                                                          int64_t prof_pitch) {
   extern __shared__ unsigned long long P_all[];  // 4 x (p + 1)
+  __shared__ double wnum[SDD_MAX_WIDTHS], wden[SDD_MAX_WIDTHS];
   const int32_t p = a.p, sr = blockIdx.y;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int32_t s = (int32_t)blockIdx.x * (kThreads / 64) + wid;
-  if (s >= a.m) return;  // whole wavefront: no workgroup barrier below
   unsigned long long* P = P_all + (int64_t)wid * (p + 1);
-  const uint32_t* row = prof + (int64_t)sr * prof_pitch + (int64_t)s * p;
-  const int32_t c = (p + 63) / 64;
-  const int32_t k0 = min(lane * c, p), k1 = min(k0 + c, p);
-  unsigned long long part = 0;
-#pragma unroll 4
-  for (int32_t k = k0; k < k1; ++k) part += row[k];
-  unsigned long long inc = part;
-  for (int o = 1; o < 64; o <<= 1) {
-    const unsigned long long t = __shfl_up(inc, o, 64);
-    if (lane >= o) inc += t;
-  }
-  unsigned long long off = inc - part;
-  for (int32_t k = k0; k < k1; ++k) {
-    P[k] = off;
-    off += row[k];
-  }
-  const unsigned long long total = __shfl(inc, 63, 64);
-  if (lane == 0) P[p] = total;
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   const uint64_t n = (uint64_t)a.m * (uint64_t)p;
   double mu, sigma;
   fold_mean_sigma(n, a.moments[2 * sr], a.moments[2 * sr + 1], &mu, &sigma);
-  double bs = 0.0;
-  int32_t bj = 0, bw = a.widths[0];
-  if (sigma > 0.0) {
-    bs = -INFINITY;
-    for (int q = 0; q < a.nwidths; ++q) {
-      const int32_t w = a.widths[q];
-      unsigned long long bb = 0ull;
-      int32_t bjj = 0x7fffffff;
-      for (int32_t j = lane; j < p; j += 64) {
-        const int32_t e = j + w;
-        const unsigned long long b = e <= p ? P[e] - P[j] : total - P[j] + P[e - p];
-        if (bj_better(b, j, bb, bjj)) {
-          bb = b;
-          bjj = j;
+  if (threadIdx.x < (unsigned)a.nwidths) {
+    const double w = (double)a.widths[threadIdx.x];
+    wnum[threadIdx.x] = w * (double)a.m * mu;
+    wden[threadIdx.x] = sigma * sqrt((double)a.m * w);
+  }
+  __syncthreads();
+  // each wavefront loops on its own: no workgroup barrier below
+  for (int32_t s = (int32_t)blockIdx.x * (kThreads / 64) + wid; s < a.m;
+       s += (int32_t)gridDim.x * (kThreads / 64)) {
+    const uint32_t* row = prof + (int64_t)sr * prof_pitch + (int64_t)s * p;
+    // the previous profile's readers of P are done
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int32_t c = (p + 63) / 64;
+    const int32_t k0 = min(lane * c, p), k1 = min(k0 + c, p);
+    unsigned long long part = 0;
+#pragma unroll 4
+    for (int32_t k = k0; k < k1; ++k) part += row[k];
+    unsigned long long inc = part;
+    for (int o = 1; o < 64; o <<= 1) {
+      const unsigned long long t = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += t;
+    }
+    unsigned long long off = inc - part;
+    for (int32_t k = k0; k < k1; ++k) {
+      P[k] = off;
+      off += row[k];
+    }
+    const unsigned long long total = __shfl(inc, 63, 64);
+    if (lane == 0) P[p] = total;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    double bs = 0.0;
+    int32_t bj = 0, bw = a.widths[0];
+    if (sigma > 0.0) {
+      bs = -INFINITY;
+      bj = 0x7fffffff;
+      for (int q = 0; q < a.nwidths; ++q) {
+        const int32_t w = a.widths[q];
+        unsigned long long bb = 0ull;
+        int32_t bjj = -1;
+        for (int32_t j = lane; j < p; j += 64) {
+          const int32_t e = j + w;
+          const unsigned long long b = e <= p ? P[e] - P[j] : total - P[j] + P[e - p];
+          if (bjj < 0 || b > bb) {
+            bb = b;
+            bjj = j;
+          }
+        }
+        if (bjj >= 0) {
+          const double sn = ((double)bb - wnum[q]) / wden[q];
+          if (snr_better(sn, bjj, w, bs, bj, bw)) {
+            bs = sn;
+            bj = bjj;
+            bw = w;
+          }
         }
       }
       for (int o = 32; o > 0; o >>= 1) {
-        const unsigned long long b2 = __shfl_xor(bb, o, 64);
-        const int32_t j2 = __shfl_xor(bjj, o, 64);
-        if (bj_better(b2, j2, bb, bjj)) {
-          bb = b2;
-          bjj = j2;
+        const double s2 = __shfl_xor(bs, o, 64);
+        const int32_t j2 = __shfl_xor(bj, o, 64);
+        const int32_t w2 = __shfl_xor(bw, o, 64);
+        if (snr_better(s2, j2, w2, bs, bj, bw)) {
+          bs = s2;
+          bj = j2;
+          bw = w2;
         }
       }
-      const double sn =
-          ((double)bb - (double)w * (double)a.m * mu) / (sigma * sqrt((double)a.m * (double)w));
-      if (sn > bs || (sn == bs && bjj < bj)) {  // widths ascend: a tie keeps the smaller
-        bs = sn;
-        bj = bjj;
-        bw = w;
-      }
     }
-  }
-  if (lane == 0) {
-    sdd_ffa_best o;
-    o.snr = (float)bs;
-    o.bin = bj;
-    o.width = bw;
-    o.pad = 0;
-    a.best[(int64_t)sr * a.m + s] = o;
-    if (s == 0 && a.stats) {
-      sdd_dm_stats st;
-      st.n = (int64_t)n;
-      st.s1 = a.moments[2 * sr];
-      st.s2 = a.moments[2 * sr + 1];
-      st.mean = mu;
-      st.std = sigma;
-      a.stats[sr] = st;
+    if (lane == 0) {
+      sdd_ffa_best o;
+      o.snr = (float)bs;
+      o.bin = bj;
+      o.width = bw;
+      o.pad = 0;
+      a.best[(int64_t)sr * a.m + s] = o;
+      if (s == 0 && a.stats) {
+        sdd_dm_stats st;
+        st.n = (int64_t)n;
+        st.s1 = a.moments[2 * sr];
+        st.s2 = a.moments[2 * sr + 1];
+        st.mean = mu;
+        st.std = sigma;
+        a.stats[sr] = st;
+      }
     }
   }
 }
@@ -356,13 +401,15 @@ int floor_log2(int64_t v) {
 int64_t round_up256(int64_t v) { return (v + 255) & ~(int64_t)255; }
 
 struct FfaLayout {
-  int64_t moments = 0, buf0 = 0, buf1 = 0, total = 0;
+  int64_t moments = 0, tab = 0, buf0 = 0, buf1 = 0, total = 0;
 };
 
+// moments [nseries] x 16 B, source tables [floor(log2 m)][m] x 16 B, two stacks
 FfaLayout ffa_layout(int32_t nseries, int64_t m, int32_t p) {
   FfaLayout L;
   L.moments = 0;
-  int64_t off = round_up256((int64_t)nseries * 16);
+  L.tab = round_up256((int64_t)nseries * 16);
+  int64_t off = L.tab + round_up256((int64_t)floor_log2(m) * m * 16);
   const int64_t stack = round_up256((int64_t)nseries * m * p * 4);
   L.buf0 = off;
   L.buf1 = off + stack;
@@ -443,6 +490,10 @@ extern "C" sdd_status sdd_ffa_search(int32_t device, const uint32_t* d_series, i
   auto height = [&](int d) { return (m + ((int64_t)1 << d) - 1) >> d; };
   while (d0 < floor_log2(m) && (height(d0) * period > kLdsElems || height(d0) > kLdsRows)) ++d0;
   const int64_t stack = m * period;
+  a.tab = reinterpret_cast<const int4*>(ws + lay.tab);
+  if (d0 > 0)
+    hipLaunchKernelGGL(k_ffa_table, dim3((unsigned)(((int64_t)d0 * m + 255) / 256)), dim3(256), 0,
+                       s, (int32_t)m, period, d0, reinterpret_cast<int4*>(ws + lay.tab));
   uint32_t* bufs[2] = {reinterpret_cast<uint32_t*>(ws + lay.buf0),
                        reinterpret_cast<uint32_t*>(ws + lay.buf1)};
   // destinations: the final level writes d_profiles when given; the others
@@ -461,17 +512,25 @@ extern "C" sdd_status sdd_ffa_search(int32_t device, const uint32_t* d_series, i
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 65536));
   SDD_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ffa_boxcar),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_b));
-  hipLaunchKernelGGL(k_ffa_lds, dim3(1u << d0, (unsigned)nseries), dim3(kThreads), lds_a, s, a,
-                     d0, cap, cur, stack);
+  hipLaunchKernelGGL(k_ffa_lds, dim3(1u << d0, (unsigned)nseries), dim3(kLdsThreads), lds_a, s,
+                     a, d0, cap, cur, stack);
+  // about 32K workgroups per pass, each with at least 16 elements per thread
   const int32_t rstep = period >= kThreads ? 1 : kThreads / period;
+  const int64_t groups = (m + rstep - 1) / rstep;
+  const int64_t per_grp = (int64_t)rstep * period;  // elements of one row group
+  const int64_t gx_pass = std::max<int64_t>(
+      1, std::min<int64_t>({groups, (32768 + nseries - 1) / nseries,
+                            (groups * per_grp) / (16 * kThreads) + 1}));
   for (int k = 1; k < nlev; ++k) {
     uint32_t* nxt = dst_of(k, nlev);
-    hipLaunchKernelGGL(k_ffa_pass, dim3((unsigned)((m + rstep - 1) / rstep), (unsigned)nseries),
-                       dim3(kThreads), 0, s, a, d0 - k, cur, stack, nxt, stack);
+    hipLaunchKernelGGL(k_ffa_pass, dim3((unsigned)gx_pass, (unsigned)nseries), dim3(kThreads), 0,
+                       s, a, d0 - k, cur, stack, nxt, stack);
     cur = nxt;
   }
-  hipLaunchKernelGGL(k_ffa_boxcar, dim3((unsigned)((m + 3) / 4), (unsigned)nseries),
-                     dim3(kThreads), lds_b, s, a, cur, stack);
+  const int64_t gx_box = std::max<int64_t>(
+      1, std::min<int64_t>((m + 3) / 4, (16384 + nseries - 1) / nseries));
+  hipLaunchKernelGGL(k_ffa_boxcar, dim3((unsigned)gx_box, (unsigned)nseries), dim3(kThreads),
+                     lds_b, s, a, cur, stack);
   SDD_HIP_TRY(hipGetLastError());
   return SDD_OK;
 }

@@ -842,6 +842,8 @@ hipError_t launch_search(const SearchArgs& a, hipStream_t s) {
       hipLaunchKernelGGL(k_dered_base<12>, gr, dim3(256), 0, s, a);
     else if (ne <= 16)
       hipLaunchKernelGGL(k_dered_base<16>, gr, dim3(256), 0, s, a);
+    else if (ne <= 20)
+      hipLaunchKernelGGL(k_dered_base<20>, gr, dim3(256), 0, s, a);
     else if (ne <= 24)
       hipLaunchKernelGGL(k_dered_base<24>, gr, dim3(256), 0, s, a);
     else if (ne <= 32)
