@@ -268,3 +268,35 @@ def test_set_dereddening_validates_and_grows_the_workspace():
     assert g["workspace_bytes"] >= w0 + 2 * ((cols + 255) // 256) * 4
     p.set_dereddening(0)
     assert p.geometry(20000)["workspace_bytes"] == w0
+
+
+def test_ffa_search_validates_before_touching_the_device():
+    """Every argument check of sdd_ffa_search runs on the host, before any
+    device call (fake non-null device addresses are never dereferenced)."""
+    L = A.lib()
+    nb = C.c_int64()
+    assert L.sdd_ffa_workspace_size(4, 100000, 1000, C.byref(nb)) == A.SDD_OK
+    m = 100
+    assert nb.value >= 4 * m * 1000 * 4 * 2 + 4 * 16
+    assert L.sdd_ffa_workspace_size(0, 100000, 1000, C.byref(nb)) == A.SDD_EINVAL
+    assert L.sdd_ffa_workspace_size(4, 999, 1000, C.byref(nb)) == A.SDD_EINVAL
+    fake = 0x10000
+    w = (C.c_int32 * 3)(1, 2, 4)
+
+    def call(nsamp=100000, period=1000, maxv=4096, widths=w, nw=3, ws=nb.value, pitch=None,
+             best=fake, series=fake):
+        return L.sdd_ffa_search(0, series, pitch or nsamp, 4, nsamp, period, maxv, widths, nw,
+                                None, best, None, fake, ws, None)
+
+    assert call(series=None) == A.SDD_EINVAL
+    assert call(best=None) == A.SDD_EINVAL
+    assert call(period=1) == A.SDD_EINVAL
+    assert call(period=4097, nsamp=100000) == A.SDD_EINVAL
+    assert call(nsamp=500) == A.SDD_EINVAL
+    assert call(pitch=99999) == A.SDD_EINVAL
+    assert call(nw=0) == A.SDD_EINVAL
+    assert call(widths=(C.c_int32 * 3)(1, 4, 2)) == A.SDD_EINVAL     # not increasing
+    assert call(widths=(C.c_int32 * 3)(1, 2, 1000)) == A.SDD_EINVAL  # not below the period
+    # m * max_value = 100 * 2^26 >= 2^32: a profile bin could overflow 32 bits
+    assert call(maxv=1 << 26) == A.SDD_ERANGE
+    assert call(ws=nb.value - 1) == A.SDD_ENOMEM
