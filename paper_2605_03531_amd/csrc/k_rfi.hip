@@ -49,6 +49,7 @@ struct RfiArgs {
   int32_t* cflag;     // [C]
   int64_t* z;         // [T] zero-DM series
   int32_t* tflag;     // [T]
+  uint8_t* keep8;     // [T] 0xff for an unflagged sample, 0 for a flagged one
   uint64_t* keys;     // [max(C, T)] selection keys
   uint64_t* sel;      // [8] selection results
   int64_t* nt;        // [1] unflagged samples
@@ -95,7 +96,16 @@ __global__ __launch_bounds__(1024) void k_select(const uint64_t* keys, int64_t n
 
 __global__ __launch_bounds__(256) void k_clear_tflag(RfiArgs a) {
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (t < a.T) a.tflag[t] = 0;
+  if (t < a.T) {
+    a.tflag[t] = 0;
+    a.keep8[t] = 0xff;
+  }
+}
+
+// Sum of the 4 bytes of w (SWAR: two 16-bit fields, then their sum).
+__device__ inline uint32_t byte_sum4(uint32_t w) {
+  const uint32_t e = (w & 0x00ff00ffu) + ((w >> 8) & 0x00ff00ffu);
+  return (e & 0xffffu) + (e >> 16);
 }
 
 // ---- unflagged sample count ----
@@ -115,6 +125,8 @@ __global__ __launch_bounds__(1024) void k_count_keep(RfiArgs a) {
 }
 
 // ---- channel means over unflagged samples (all when none is unflagged) ----
+// VEC: rows 16-byte aligned: 16 samples per load, masked with keep8.
+template <bool VEC>
 __global__ __launch_bounds__(256) void k_chan_mean(RfiArgs a) {
   __shared__ unsigned long long part[4];
   const int32_t c = blockIdx.x;
@@ -123,7 +135,19 @@ __global__ __launch_bounds__(256) void k_chan_mean(RfiArgs a) {
   const bool all = nt == 0;
   const uint8_t* row = a.rows + (int64_t)c * a.pitch;
   unsigned long long s = 0;
-  for (int64_t t = tid; t < a.T; t += 256)
+  int64_t t0 = 0;
+  if constexpr (VEC) {
+    const int64_t nv = a.T / 16;
+    const uint32_t any = all ? 0xffffffffu : 0u;
+    for (int64_t v = tid; v < nv; v += 256) {
+      const uint4 x = reinterpret_cast<const uint4*>(row)[v];
+      const uint4 k = reinterpret_cast<const uint4*>(a.keep8)[v];
+      s += byte_sum4(x.x & (k.x | any)) + byte_sum4(x.y & (k.y | any)) +
+           byte_sum4(x.z & (k.z | any)) + byte_sum4(x.w & (k.w | any));
+    }
+    t0 = nv * 16;
+  }
+  for (int64_t t = t0 + tid; t < a.T; t += 256)
     if (all || !a.tflag[t]) s += row[t];
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
   if ((tid & 63) == 0) part[tid >> 6] = s;
@@ -175,14 +199,49 @@ __global__ __launch_bounds__(256) void k_cflag(RfiArgs a) {
 }
 
 // ---- zero-DM series over unflagged channels ----
+// Zero-DM series: blockIdx.y takes channels [64 y, 64 y + 64); each thread 4
+// consecutive samples (one 32-bit load per channel when VEC: rows 4-byte
+// aligned), added into z with integer atomics (z cleared first).
+template <bool VEC>
 __global__ __launch_bounds__(256) void k_zero_dm(RfiArgs a) {
-  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t t = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
   if (t >= a.T) return;
-  int64_t s = 0;
-  for (int32_t c = 0; c < a.C; ++c)
-    if (!a.cflag[c]) s += a.rows[(int64_t)c * a.pitch + t];
-  a.z[t] = s;
-  a.keys[t] = (uint64_t)s;
+  const int32_t c0 = blockIdx.y * 64, c1 = min(c0 + 64, a.C);
+  uint32_t s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  if (VEC && t + 4 <= a.T) {
+    for (int32_t c = c0; c < c1; ++c) {
+      if (a.cflag[c]) continue;
+      const uint32_t w = *reinterpret_cast<const uint32_t*>(a.rows + (int64_t)c * a.pitch + t);
+      s0 += w & 255u;
+      s1 += (w >> 8) & 255u;
+      s2 += (w >> 16) & 255u;
+      s3 += w >> 24;
+    }
+  } else {
+    for (int32_t c = c0; c < c1; ++c) {
+      if (a.cflag[c]) continue;
+      const uint8_t* r = a.rows + (int64_t)c * a.pitch + t;
+      s0 += r[0];
+      if (t + 1 < a.T) s1 += r[1];
+      if (t + 2 < a.T) s2 += r[2];
+      if (t + 3 < a.T) s3 += r[3];
+    }
+  }
+  unsigned long long* z = reinterpret_cast<unsigned long long*>(a.z);
+  atomicAdd(&z[t], (unsigned long long)s0);
+  if (t + 1 < a.T) atomicAdd(&z[t + 1], (unsigned long long)s1);
+  if (t + 2 < a.T) atomicAdd(&z[t + 2], (unsigned long long)s2);
+  if (t + 3 < a.T) atomicAdd(&z[t + 3], (unsigned long long)s3);
+}
+
+__global__ __launch_bounds__(256) void k_clear_z(RfiArgs a) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t < a.T) a.z[t] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_z_keys(RfiArgs a) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t < a.T) a.keys[t] = (uint64_t)a.z[t];
 }
 
 __global__ __launch_bounds__(256) void k_absdev_i64(RfiArgs a) {
@@ -198,7 +257,9 @@ __global__ __launch_bounds__(256) void k_tflag(RfiArgs a) {
   const int64_t med = (int64_t)a.sel[2];
   const double sig = kMadScale * (double)(int64_t)a.sel[3];
   const int64_t d = a.z[t] - med;
-  a.tflag[t] = (sig > 0.0 && (double)(d < 0 ? -d : d) > a.k_time * sig) ? 1 : 0;
+  const bool flag = sig > 0.0 && (double)(d < 0 ? -d : d) > a.k_time * sig;
+  a.tflag[t] = flag ? 1 : 0;
+  a.keep8[t] = flag ? 0 : 0xff;
 }
 
 __global__ __launch_bounds__(256) void k_bp_keys(RfiArgs a) {
@@ -227,7 +288,7 @@ int64_t align256(int64_t v) { return (v + 255) / 256 * 256; }
 
 struct RfiLayout {
   int64_t rows = -1, rows_pitch = 0;
-  int64_t m, b, r, cflag, z, tflag, keys, sel, nt, total;
+  int64_t m, b, r, cflag, z, tflag, keep8, keys, sel, nt, total;
 };
 
 RfiLayout rfi_layout(const sdd_plan* p, int64_t T) {
@@ -249,6 +310,7 @@ RfiLayout rfi_layout(const sdd_plan* p, int64_t T) {
   L.cflag = take(4 * C);
   L.z = take(8 * T);
   L.tflag = take(4 * T);
+  L.keep8 = take(T);
   L.keys = take(8 * std::max<int64_t>(C, T));
   L.sel = take(8 * 8);
   L.nt = take(8);
@@ -318,12 +380,16 @@ extern "C" sdd_status sdd_rfi_estimate(const sdd_plan* p, const uint8_t* d_in, i
   a.cflag = (int32_t*)(w + L.cflag);
   a.z = (int64_t*)(w + L.z);
   a.tflag = (int32_t*)(w + L.tflag);
+  a.keep8 = w + L.keep8;
   a.keys = (uint64_t*)(w + L.keys);
   a.sel = (uint64_t*)(w + L.sel);
   a.nt = (int64_t*)(w + L.nt);
 
   const int64_t C = p->nchan, T = nsamp_in;
   const dim3 gC((unsigned)((C + 255) / 256)), gT((unsigned)((T + 255) / 256)), b256(256);
+  const dim3 gZ((unsigned)((T + 1023) / 1024), (unsigned)((C + 63) / 64));
+  const bool vec16 = (uintptr_t)a.rows % 16 == 0 && a.pitch % 16 == 0;
+  const bool vec4 = (uintptr_t)a.rows % 4 == 0 && a.pitch % 4 == 0;
   // largest zero-DM sum C * 255 fixes how many key bytes the selections scan
   int ztop = 0;
   for (uint64_t zmax = (uint64_t)C * 255u; zmax >> (8 * (ztop + 1)); ++ztop) {
@@ -332,14 +398,22 @@ extern "C" sdd_status sdd_rfi_estimate(const sdd_plan* p, const uint8_t* d_in, i
   hipLaunchKernelGGL(k_clear_tflag, gT, b256, 0, s, a);
   for (int round = 0; round < desc->rounds; ++round) {
     hipLaunchKernelGGL(k_count_keep, dim3(1), dim3(1024), 0, s, a);
-    hipLaunchKernelGGL(k_chan_mean, dim3((unsigned)C), b256, 0, s, a);
+    if (vec16)
+      hipLaunchKernelGGL(k_chan_mean<true>, dim3((unsigned)C), b256, 0, s, a);
+    else
+      hipLaunchKernelGGL(k_chan_mean<false>, dim3((unsigned)C), b256, 0, s, a);
     hipLaunchKernelGGL(k_bandpass, gC, b256, 0, s, a);
     hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, s, a.keys, C, (C - 1) / 2, 7, a.sel + 0);
     hipLaunchKernelGGL(k_absdev_f64, gC, b256, 0, s, a, (const double*)a.r, (int32_t)C,
                        (const uint64_t*)(a.sel + 0));
     hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, s, a.keys, C, (C - 1) / 2, 7, a.sel + 1);
     hipLaunchKernelGGL(k_cflag, gC, b256, 0, s, a);
-    hipLaunchKernelGGL(k_zero_dm, gT, b256, 0, s, a);
+    hipLaunchKernelGGL(k_clear_z, gT, b256, 0, s, a);
+    if (vec4)
+      hipLaunchKernelGGL(k_zero_dm<true>, gZ, b256, 0, s, a);
+    else
+      hipLaunchKernelGGL(k_zero_dm<false>, gZ, b256, 0, s, a);
+    hipLaunchKernelGGL(k_z_keys, gT, b256, 0, s, a);
     hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, s, a.keys, T, (T - 1) / 2, ztop,
                        a.sel + 2);
     hipLaunchKernelGGL(k_absdev_i64, gT, b256, 0, s, a);

@@ -33,9 +33,12 @@ def _plan(C, layout, **kw):
 
 
 @pytest.mark.parametrize("layout", ["chan", "time"])
-def test_rfi_estimate_equals_oracle(layout):
+@pytest.mark.parametrize("T", [6000, 6003])
+def test_rfi_estimate_equals_oracle(layout, T):
+    """T = 6000: vector loads of channel rows; T = 6003: unaligned
+    channel-major rows (byte loads) and a 3-sample tail after the corner turn."""
     import torch
-    C, T = 256, 6000
+    C = 256
     x = _chunk(12, C, T)
     plan, _ = _plan(C, layout)
     xin = torch.from_numpy(x if layout == "chan" else synth.to_time_major(x)).to("cuda:0")
