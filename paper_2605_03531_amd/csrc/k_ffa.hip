@@ -293,7 +293,7 @@ __device__ inline bool snr_better(double s, int32_t j, int32_t w, double s2, int
 // the search's order; one wave reduction in the same order ends the profile.
 __global__ __launch_bounds__(kThreads) void k_ffa_boxcar(FfaArgs a, const uint32_t* prof,
                                                          int64_t prof_pitch) {
-  extern __shared__ unsigned long long P_all[];  // 4 x (p + 1)
+  extern __shared__ unsigned long long P_all[];  // 4 x (p + 1): u64 prefix or u32 p + w_max
   __shared__ double wnum[SDD_MAX_WIDTHS], wden[SDD_MAX_WIDTHS];
   const int32_t p = a.p, sr = blockIdx.y;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -318,49 +318,120 @@ __global__ __launch_bounds__(kThreads) void k_ffa_boxcar(FfaArgs a, const uint32
     const int32_t c = (p + 63) / 64;
     const int32_t k0 = min(lane * c, p), k1 = min(k0 + c, p);
     unsigned long long part = 0;
+    uint32_t lmin = 0xffffffffu;
 #pragma unroll 4
-    for (int32_t k = k0; k < k1; ++k) part += row[k];
+    for (int32_t k = k0; k < k1; ++k) {
+      const uint32_t v = row[k];
+      part += v;
+      lmin = min(lmin, v);
+    }
     unsigned long long inc = part;
     for (int o = 1; o < 64; o <<= 1) {
       const unsigned long long t = __shfl_up(inc, o, 64);
       if (lane >= o) inc += t;
     }
-    unsigned long long off = inc - part;
-    for (int32_t k = k0; k < k1; ++k) {
-      P[k] = off;
-      off += row[k];
-    }
+    for (int o = 32; o > 0; o >>= 1) lmin = min(lmin, (uint32_t)__shfl_xor((int)lmin, o, 64));
+    const uint32_t base = lmin;  // the profile's smallest bin
     const unsigned long long total = __shfl(inc, 63, 64);
-    if (lane == 0) P[p] = total;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // bins minus the smallest one: when their total fits 32 bits (the usual
+    // case) the prefix of the offset bins is exact in uint32 and every boxcar
+    // of them too; B = B' + w * base
+    const bool narrow = total - (unsigned long long)p * base < (1ull << 32);
     double bs = 0.0;
     int32_t bj = 0, bw = a.widths[0];
-    if (sigma > 0.0) {
-      bs = -INFINITY;
-      bj = 0x7fffffff;
-      for (int q = 0; q < a.nwidths; ++q) {
-        const int32_t w = a.widths[q];
-        unsigned long long bb = 0ull;
-        int32_t bjj = -1;
-        for (int32_t j = lane; j < p; j += 64) {
-          const int32_t e = j + w;
-          const unsigned long long b = e <= p ? P[e] - P[j] : total - P[j] + P[e - p];
-          if (bjj < 0 || b > bb) {
-            bb = b;
-            bjj = j;
+    if (narrow) {
+      uint32_t* Q = reinterpret_cast<uint32_t*>(P);  // p + w_max entries
+      uint32_t off = (uint32_t)(inc - part) - (uint32_t)k0 * base;
+      for (int32_t k = k0; k < k1; ++k) {
+        Q[k] = off;
+        off += row[k] - base;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      // circular extension: Q[p + k] = Q[p] + Q[k]
+      const uint32_t qtot = (uint32_t)(total - (unsigned long long)p * base);
+      const int32_t wmax = a.widths[a.nwidths - 1];
+      for (int32_t k = lane; k < wmax; k += 64) Q[p + k] = qtot + Q[k];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (sigma > 0.0) {
+        bs = -INFINITY;
+        bj = 0x7fffffff;
+        for (int q0 = 0; q0 < a.nwidths; q0 += 8) {
+          uint32_t bb[8];
+          int32_t bjj[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            bb[u] = 0u;
+            bjj[u] = -1;
           }
-        }
-        if (bjj >= 0) {
-          const double sn = ((double)bb - wnum[q]) / wden[q];
-          if (snr_better(sn, bjj, w, bs, bj, bw)) {
-            bs = sn;
-            bj = bjj;
-            bw = w;
+          for (int32_t j = lane; j < p; j += 64) {
+            const uint32_t qj = Q[j];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              if (q0 + u < a.nwidths) {
+                const uint32_t b = Q[j + a.widths[q0 + u]] - qj;
+                if (bjj[u] < 0 || b > bb[u]) {
+                  bb[u] = b;
+                  bjj[u] = j;
+                }
+              }
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            if (q0 + u < a.nwidths && bjj[u] >= 0) {
+              const int32_t w = a.widths[q0 + u];
+              const unsigned long long B = (unsigned long long)bb[u] + (unsigned long long)w * base;
+              const double sn = ((double)B - wnum[q0 + u]) / wden[q0 + u];
+              if (snr_better(sn, bjj[u], w, bs, bj, bw)) {
+                bs = sn;
+                bj = bjj[u];
+                bw = w;
+              }
+            }
           }
         }
       }
+    } else {
+      unsigned long long off = inc - part;
+      for (int32_t k = k0; k < k1; ++k) {
+        P[k] = off;
+        off += row[k];
+      }
+      if (lane == 0) P[p] = total;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (sigma > 0.0) {
+        bs = -INFINITY;
+        bj = 0x7fffffff;
+        for (int q = 0; q < a.nwidths; ++q) {
+          const int32_t w = a.widths[q];
+          unsigned long long bb = 0ull;
+          int32_t bjj = -1;
+          for (int32_t j = lane; j < p; j += 64) {
+            const int32_t e = j + w;
+            const unsigned long long b = e <= p ? P[e] - P[j] : total - P[j] + P[e - p];
+            if (bjj < 0 || b > bb) {
+              bb = b;
+              bjj = j;
+            }
+          }
+          if (bjj >= 0) {
+            const double sn = ((double)bb - wnum[q]) / wden[q];
+            if (snr_better(sn, bjj, w, bs, bj, bw)) {
+              bs = sn;
+              bj = bjj;
+              bw = w;
+            }
+          }
+        }
+      }
+    }
+    if (sigma > 0.0) {
       for (int o = 32; o > 0; o >>= 1) {
         const double s2 = __shfl_xor(bs, o, 64);
         const int32_t j2 = __shfl_xor(bj, o, 64);

@@ -172,3 +172,21 @@ def test_full_band_plane_sampled_trials():
         rel = _check(yk[None, :].astype(np.uint32), 1024, widths,
                      (best[i:i + 1], None, st[i:i + 1]), f"full band row {i}")
         say(f"row {i}: S/N rel err {rel:.2e}")
+
+
+def test_wide_profiles_take_the_64_bit_boxcar_path():
+    """Samples up to 2^25 at a 4096-bin period: a profile's bins minus its
+    smallest bin total far above 2^32, so the boxcar search runs on 64-bit
+    prefix sums; one series of small values in the same call stays on the
+    32-bit path."""
+    import torch
+    import paper_2605_03531_amd as sdd
+    g = np.random.Generator(np.random.PCG64(31))
+    y = g.integers(0, 1 << 25, (3, 8192 + 17)).astype(np.uint32)
+    y[1] = g.integers(0, 1000, 8192 + 17).astype(np.uint32)
+    x = torch.from_numpy(y.view(np.int32)).to("cuda:0")
+    widths = [1, 3, 64, 1000, 4095]
+    out = sdd.ffa_search(x, 4096, widths, (1 << 25) - 1, profiles=True)
+    torch.cuda.synchronize()
+    rel = _check(y, 4096, widths, out.host(), "wide")
+    say(f"wide profiles: S/N rel err {rel:.2e}")
