@@ -475,12 +475,23 @@ struct FfaLayout {
   int64_t moments = 0, tab = 0, buf0 = 0, buf1 = 0, total = 0;
 };
 
-// moments [nseries] x 16 B, source tables [floor(log2 m)][m] x 16 B, two stacks
+// Depth of the sub-stacks that k_ffa_lds folds: the shallowest whose
+// sub-stacks hold at most kLdsRows rows and kLdsElems bins (every row still
+// belongs to a sub-stack there: depth <= floor(log2 m)). The levels above it
+// are the HBM passes.
+int lds_depth(int64_t m, int32_t p) {
+  auto height = [&](int d) { return (m + ((int64_t)1 << d) - 1) >> d; };
+  int d0 = 0;
+  while (d0 < floor_log2(m) && (height(d0) * p > kLdsElems || height(d0) > kLdsRows)) ++d0;
+  return d0;
+}
+
+// moments [nseries] x 16 B, source tables [d0][m] x 16 B, two stacks
 FfaLayout ffa_layout(int32_t nseries, int64_t m, int32_t p) {
   FfaLayout L;
   L.moments = 0;
   L.tab = round_up256((int64_t)nseries * 16);
-  int64_t off = L.tab + round_up256((int64_t)floor_log2(m) * m * 16);
+  int64_t off = L.tab + round_up256((int64_t)lds_depth(m, p) * m * 16);
   const int64_t stack = round_up256((int64_t)nseries * m * p * 4);
   L.buf0 = off;
   L.buf1 = off + stack;
@@ -555,11 +566,8 @@ extern "C" sdd_status sdd_ffa_search(int32_t device, const uint32_t* d_series, i
   const unsigned gx = (unsigned)std::max<int64_t>(1, std::min<int64_t>(64, nfold / 8192));
   hipLaunchKernelGGL(k_ffa_moments, dim3(gx, (unsigned)nseries), dim3(kThreads), 0, s, a);
 
-  // lowest levels in LDS: the shallowest depth whose sub-stacks fit (every
-  // row still belongs to a sub-stack there: depth <= floor(log2 m))
-  int d0 = 0;
+  const int d0 = lds_depth(m, period);
   auto height = [&](int d) { return (m + ((int64_t)1 << d) - 1) >> d; };
-  while (d0 < floor_log2(m) && (height(d0) * period > kLdsElems || height(d0) > kLdsRows)) ++d0;
   const int64_t stack = m * period;
   a.tab = reinterpret_cast<const int4*>(ws + lay.tab);
   if (d0 > 0)
