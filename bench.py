@@ -243,9 +243,9 @@ def ffa_bench(sdd, torch, plane, n_owned: int, reps: int = 3):
 
 
 def serve_bench(sdd, torch, nbeams: int, sat_chunks: int, rt_periods: int, max_batch: int,
-                nstreams: int, per_item: bool = True):
-    """Streaming server with nbeams beams (1024/2048/4096 channels by beam
-    index mod 3), 2^16-sample chunks, 2048 DM trials 0-1000, widths 1..64.
+                nstreams: int, per_item: bool = True, chans=(1024, 2048, 4096)):
+    """Streaming server with nbeams beams (channel counts from `chans` by beam
+    index), 2^16-sample chunks, 2048 DM trials 0-1000, widths 1..64.
 
     Saturated run: every beam submits sat_chunks chunks as fast as the rings
     allow; capacity = beams x stream seconds / wall seconds. Real-time run:
@@ -256,7 +256,7 @@ def serve_bench(sdd, torch, nbeams: int, sat_chunks: int, rt_periods: int, max_b
     N = 1 << 16
     t_samp = 81.92e-6
     period = N * t_samp
-    chans = [1024, 2048, 4096]
+    chans = list(chans)
     dms = np.linspace(0.0, 1000.0, 2048)
     plans = {C: sdd.Plan(np.linspace(750.0, 550.0, C), t_samp, dm_list=dms, widths=WIDTHS,
                          cand_block=1024, threshold=7.0, layout="time") for C in chans}
@@ -265,7 +265,7 @@ def serve_bench(sdd, torch, nbeams: int, sat_chunks: int, rt_periods: int, max_b
     for C in chans:
         x = synth.filterbank(900 + C, C, pool_n * N, 128.0, 16.0)
         pools[C] = torch.from_numpy(synth.to_time_major(x)).to("cuda:0")
-    beam_c = [chans[b % 3] for b in range(nbeams)]
+    beam_c = [chans[b % len(chans)] for b in range(nbeams)]
 
     def run(chunks_per_beam, realtime, measure_from):
         srv = sdd.Server(hbm_budget=250 << 30, max_beams=nbeams, nstreams=nstreams,
@@ -310,7 +310,9 @@ def serve_bench(sdd, torch, nbeams: int, sat_chunks: int, rt_periods: int, max_b
     log(f"serving: {outputs} chunk results in {wall:.2f} s; capacity {capacity:.1f} beams; "
         f"{stats['batches']} batches")
     out = {"beams": nbeams, "chunk_samples": N, "chunk_seconds": round(period, 4),
-           "channel_mix": "1024/2048/4096 by beam index mod 3", "ndm": 2048, "widths": WIDTHS,
+           "channel_mix": ("/".join(map(str, chans)) + f" by beam index mod {len(chans)}"
+                           if len(chans) > 1 else f"{chans[0]} on every beam"),
+           "ndm": 2048, "widths": WIDTHS,
            "max_batch": max_batch, "slots": nstreams,
            "batch_launch": "one grid launch per chunk" if per_item else "persistent multi-chunk",
            "saturated": {"chunks_per_beam": sat_chunks, "results": outputs,
@@ -505,6 +507,7 @@ def main() -> int:
         log("timing the oracle on a bounded sample")
         res["cpu_baseline"] = cpu_baseline(w, plan.delays(0), args.cpu_rows)
     res["serving"] = None
+    res["serving_4096"] = None
     res["batched"] = None
     del xt, planes, ws, out
     torch.cuda.empty_cache()
@@ -514,6 +517,11 @@ def main() -> int:
     if not args.no_serve:
         res["serving"] = serve_bench(sdd, torch, args.serve_beams, args.serve_chunks,
                                      args.serve_periods, args.serve_batch, 2)
+        torch.cuda.empty_cache()
+        # the same loop with every beam at the full 4096 channels
+        res["serving_4096"] = serve_bench(sdd, torch, args.serve_beams, args.serve_chunks,
+                                          args.serve_periods, args.serve_batch, 2,
+                                          chans=(4096,))
     print(json.dumps(res), flush=True)
     return 0
 
