@@ -240,6 +240,11 @@ sdd_status sdd_autotune(sdd_plan* plan, int64_t nsamp_in, const char* cache_path
 
 /* ---- compute (enqueue on stream) ---------------------------------------- */
 
+/* Every device workspace passed to this library (d_workspace / d_ws) must be
+ * 256-byte aligned, as hipMalloc and torch allocations are: it holds 64-bit
+ * atomics and 128-bit vectors at 256-byte offsets. A misaligned workspace is
+ * refused with EINVAL before anything is enqueued. */
+
 /* Dedisperses one chunk (Section 3.2, Section 2.1): corner turn (time-major
  * input), decimation (ranges with dec > 1), then every range's plane.
  *   d_in       uint8 input, layout as planned, nsamp_in samples per channel

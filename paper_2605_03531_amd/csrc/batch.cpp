@@ -189,6 +189,7 @@ extern "C" sdd_status sdd_batch_dedisperse_search(const sdd_batch_item* items, i
   if (!d_ws || ws_bytes < need)
     SDD_FAIL(SDD_ENOMEM, "batch workspace %lld bytes < %lld needed", (long long)ws_bytes,
              (long long)need);
+  SDD_CHECK_WS_ALIGN(d_ws);
   for (int32_t k = 0; k < n; ++k) {
     const sdd_batch_item& it = items[k];
     if ((st = check_input(it.plan, it.d_in, it.nsamp_in, it.in_pitch)) != SDD_OK) return st;

@@ -209,6 +209,7 @@ extern "C" sdd_status sdd_dedisperse(const sdd_plan* p, const uint8_t* d_in, int
   if (ws_bytes < cg.ws.total || (cg.ws.total > 0 && !d_ws))
     SDD_FAIL(SDD_ENOMEM, "workspace %lld bytes < %lld needed", (long long)ws_bytes,
              (long long)cg.ws.total);
+  SDD_CHECK_WS_ALIGN(d_ws);
   DeviceGuard dg(p->device);
   if (!dg.ok) SDD_FAIL(SDD_EDEVICE, "cannot select device %d", p->device);
   if ((st = plan_upload(p)) != SDD_OK) return st;
@@ -233,6 +234,7 @@ extern "C" sdd_status sdd_search_boxcar(const sdd_plan* p, const uint32_t* const
   if (ws_bytes < cg.ws.total || !d_ws)
     SDD_FAIL(SDD_ENOMEM, "workspace %lld bytes < %lld needed", (long long)ws_bytes,
              (long long)cg.ws.total);
+  SDD_CHECK_WS_ALIGN(d_ws);
   DeviceGuard dg(p->device);
   if (!dg.ok) SDD_FAIL(SDD_EDEVICE, "cannot select device %d", p->device);
   if ((st = plan_upload(p)) != SDD_OK) return st;
@@ -263,6 +265,7 @@ extern "C" sdd_status sdd_dedisperse_search(const sdd_plan* p, const uint8_t* d_
   if (ws_bytes < need || !d_ws)
     SDD_FAIL(SDD_ENOMEM, "workspace %lld bytes < %lld needed", (long long)ws_bytes,
              (long long)need);
+  SDD_CHECK_WS_ALIGN(d_ws);
   if (lib_planes) {
     for (size_t r = 0; r < p->ranges.size(); ++r) {
       own[r] = reinterpret_cast<uint32_t*>((uint8_t*)d_ws + cg.ws.plane_off[r]);

@@ -144,8 +144,8 @@ __device__ inline RowLane row_lane(int32_t p) {
 }
 
 // The lowest levels of one sub-stack (node `blockIdx.x` at depth d0, of at
-// most kLdsRows and kLdsElems / p rows) from the input rows to its profiles, written to
-// dst (series stride dst_pitch).
+// most kLdsRows and kLdsElems / p rows) from the input rows to its profiles,
+// written to dst (series stride dst_pitch).
 __global__ __launch_bounds__(kLdsThreads) void k_ffa_lds(FfaArgs a, int d0, int32_t cap,
                                                          uint32_t* dst, int64_t dst_pitch) {
   extern __shared__ uint32_t sm[];  // 2 * cap, cap >= rows of the sub-stack * p
@@ -542,6 +542,7 @@ extern "C" sdd_status sdd_ffa_search(int32_t device, const uint32_t* d_series, i
   const FfaLayout lay = ffa_layout(nseries, m, period);
   if (ws_bytes < lay.total)
     SDD_FAIL(SDD_ENOMEM, "FFA workspace needs %lld bytes", (long long)lay.total);
+  SDD_CHECK_WS_ALIGN(d_ws);
   DeviceGuard dg(device);
   if (!dg.ok) SDD_FAIL(SDD_EDEVICE, "cannot select device %d", device);
   hipStream_t s = (hipStream_t)stream;

@@ -354,6 +354,7 @@ extern "C" sdd_status sdd_rfi_estimate(const sdd_plan* p, const uint8_t* d_in, i
   if (ws_bytes < L.total)
     SDD_FAIL(SDD_ENOMEM, "workspace %lld bytes < %lld needed", (long long)ws_bytes,
              (long long)L.total);
+  SDD_CHECK_WS_ALIGN(d_ws);
   DeviceGuard dg(p->device);
   if (!dg.ok) SDD_FAIL(SDD_EDEVICE, "cannot select device %d", p->device);
   hipStream_t s = (hipStream_t)stream;
@@ -463,6 +464,7 @@ extern "C" sdd_status sdd_dedisperse_search_pre(
   if (ws_bytes < need || !d_ws)
     SDD_FAIL(SDD_ENOMEM, "workspace %lld bytes < %lld needed", (long long)ws_bytes,
              (long long)need);
+  SDD_CHECK_WS_ALIGN(d_ws);
   uint32_t* own[SDD_MAX_RANGES];
   int64_t own_pitch[SDD_MAX_RANGES];
   if (lib_planes) {

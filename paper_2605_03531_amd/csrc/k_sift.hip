@@ -304,6 +304,7 @@ extern "C" sdd_status sdd_sift_candidates(const sdd_plan* plan, const sdd_candid
     SDD_FAIL(SDD_EINVAL, "negative or NaN clustering neighbourhood");
   if (ws_bytes < sift_ws_bytes(cap))
     SDD_FAIL(SDD_ENOMEM, "sift workspace needs %lld bytes", (long long)sift_ws_bytes(cap));
+  SDD_CHECK_WS_ALIGN(d_workspace);
   DeviceGuard dg(plan->device);
   if (!dg.ok) SDD_FAIL(SDD_EDEVICE, "cannot select device %d", plan->device);
   sdd_status st = plan_upload(plan);

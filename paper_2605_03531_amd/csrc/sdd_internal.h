@@ -33,6 +33,13 @@ void clear_error();
     return code;                     \
   } while (0)
 
+// Workspaces hold 64-bit atomics and 128-bit vectors at 256-byte offsets.
+#define SDD_CHECK_WS_ALIGN(ws)                                                   \
+  do {                                                                           \
+    if ((ws) && reinterpret_cast<uintptr_t>(ws) % 256 != 0)                      \
+      SDD_FAIL(SDD_EINVAL, "the workspace must be 256-byte aligned");           \
+  } while (0)
+
 constexpr double kDispersionConstant = 4.148808e3;  // s MHz^2 pc^-1 cm^3
 // Device delay tables are padded with zero rows to a multiple of this many
 // channels, so a kernel stage of up to this many channels reads them unmasked.

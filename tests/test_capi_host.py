@@ -300,3 +300,21 @@ def test_ffa_search_validates_before_touching_the_device():
     # m * max_value = 100 * 2^26 >= 2^32: a profile bin could overflow 32 bits
     assert call(maxv=1 << 26) == A.SDD_ERANGE
     assert call(ws=nb.value - 1) == A.SDD_ENOMEM
+
+
+def test_misaligned_workspaces_are_refused():
+    """Every entry point that takes a device workspace refuses one that is
+    not 256-byte aligned, before touching the device (fake addresses)."""
+    L = A.lib()
+    fake = 0x10000
+    w = (C.c_int32 * 1)(1)
+    nb = C.c_int64()
+    assert L.sdd_ffa_workspace_size(1, 1000, 100, C.byref(nb)) == A.SDD_OK
+    assert L.sdd_ffa_search(0, fake, 1000, 1, 1000, 100, 255, w, 1, None, fake, None, fake + 8,
+                            nb.value, None) == A.SDD_EINVAL
+    assert "aligned" in A.lib().sdd_last_error().decode()
+    assert L.sdd_sift_workspace_size(16, C.byref(nb)) == A.SDD_OK
+    p = sdd.Plan([500.0, 300.0], 1e-3, dm_list=[0.0, 5.0], widths=[1])
+    d = A.SiftDesc()
+    assert L.sdd_sift_candidates(p.handle, fake, fake, 16, C.byref(d), fake, fake, None,
+                                 fake + 64, nb.value, None) == A.SDD_EINVAL
