@@ -452,13 +452,27 @@ __global__ __launch_bounds__(64) void k_seg(SearchArgs a) {
   }
 }
 
+// Number of window samples <= v over the wavefront (absent ones are all-ones).
+template <int E>
+__device__ inline int64_t count_le(const uint32_t (&x)[E], uint32_t v) {
+  int64_t c = 0;
+#pragma unroll
+  for (int e = 0; e < E; ++e) c += __popcll(__ballot(x[e] <= v));
+  return c;
+}
+
 // Baselines of one trial's de-reddening blocks: block k gets the lower median
 // of the samples of blocks k-h..k+h (clipped to the L = N_r + w_max - 1
-// columns). One wavefront per block: the window sits in registers (lane l
-// holds samples lo + 64 e + l, e < E; absent ones read all-ones, above any
-// sample), and a bisection on the value between the window's minimum and
-// maximum counts the samples <= mid with ballots. Exact: the result is the
-// smallest v with more than rank samples <= v, a sample of the window.
+// columns). Each wavefront takes a run of consecutive blocks; the window of
+// a block sits in registers (lane l holds samples lo + 64 e + l, e < E;
+// absent ones read all-ones, above any sample), and a bisection on the value
+// counts the samples <= mid with ballots. The first block of a run bisects
+// between the window's minimum and maximum; the next ones first test a
+// bracket [prev - b, prev + b] around the previous baseline (two counts; b
+// twice the last change plus 16, at most 1024) and bisect inside it, or on
+// the side the tests point to. Exact: the
+// result is the smallest v with more than rank samples <= v, a sample of the
+// window, whatever bracket is tried.
 template <int E>
 __global__ __launch_bounds__(256) void k_dered_base(SearchArgs a) {
   const int32_t g = blockIdx.x;
@@ -470,35 +484,61 @@ __global__ __launch_bounds__(256) void k_dered_base(SearchArgs a) {
   const int64_t nb = (L + (1 << sh) - 1) >> sh;
   uint32_t* base = reinterpret_cast<uint32_t*>(a.ws + a.dered_off) + (int64_t)g * a.dered_nb;
   const int lane = threadIdx.x & 63;
-  for (int64_t k = (int64_t)blockIdx.y * 4 + (threadIdx.x >> 6); k < nb;
-       k += (int64_t)gridDim.y * 4) {
+  const int64_t waves = (int64_t)gridDim.y * 4;
+  const int64_t run = (nb + waves - 1) / waves;
+  const int64_t kb = ((int64_t)blockIdx.y * 4 + (threadIdx.x >> 6)) * run;
+  const int64_t ke = min<int64_t>(nb, kb + run);
+  uint32_t prev = 0, bw = 128;
+  for (int64_t k = kb; k < ke; ++k) {
     const int64_t lo = max<int64_t>(0, (k - h) << sh);
     const int64_t hi = min<int64_t>(L, (k + h + 1) << sh);
     uint32_t x[E];
-    uint32_t mn = 0xffffffffu, mx = 0u;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int64_t j = lo + 64 * e + lane;
       x[e] = j < hi ? row[j] : 0xffffffffu;
-      if (j < hi) {
-        mn = min(mn, x[e]);
-        mx = max(mx, x[e]);
+    }
+    const int64_t rank = (hi - lo - 1) / 2;
+    // samples are below 2^30: prev + bw cannot wrap
+    bool full = k == kb;
+    uint32_t vlo = 0, vhi = 0;
+    bool need_min = false, need_max = false;
+    if (!full) {
+      const uint32_t blo = prev > bw ? prev - bw : 0u;
+      const uint32_t bhi = prev + bw;
+      if (count_le(x, bhi) <= rank) {  // the median lies above the bracket
+        vlo = bhi + 1;
+        need_max = true;
+      } else if (blo > 0 && count_le(x, blo - 1) > rank) {  // below it
+        vhi = blo - 1;
+        need_min = true;
+      } else {
+        vlo = blo;
+        vhi = bhi;
       }
     }
-    mn = ~wave_max_u32(~mn);
-    mx = wave_max_u32(mx);
-    const int64_t rank = (hi - lo - 1) / 2;
-    uint32_t vlo = mn, vhi = mx;
+    if (full || need_min || need_max) {
+      uint32_t mn = 0xffffffffu, mx = 0u;
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+        if (lo + 64 * e + lane < hi) {
+          mn = min(mn, x[e]);
+          mx = max(mx, x[e]);
+        }
+      mn = ~wave_max_u32(~mn);
+      mx = wave_max_u32(mx);
+      if (full || need_min) vlo = mn;
+      if (full || need_max) vhi = mx;
+    }
     while (vlo < vhi) {
       const uint32_t mid = vlo + (vhi - vlo) / 2;
-      int64_t c = 0;
-#pragma unroll
-      for (int e = 0; e < E; ++e) c += __popcll(__ballot(x[e] <= mid));
-      if (c > rank)
+      if (count_le(x, mid) > rank)
         vhi = mid;
       else
         vlo = mid + 1;
     }
+    if (!full) bw = min(1024u, 2u * (vlo > prev ? vlo - prev : prev - vlo) + 16u);
+    prev = vlo;
     if (lane == 0) base[k] = vlo;
   }
 }
@@ -831,8 +871,9 @@ hipError_t launch_search(const SearchArgs& a, hipStream_t s) {
       nb = std::max<int64_t>(nb, (a.r[r].n_owned + a.w_max - 1 + (1 << a.dered_shift) - 1) >>
                                      a.dered_shift);
     if (nb > a.dered_nb) return hipErrorInvalidValue;
+    // runs of about 16 consecutive blocks per wavefront, 4 wavefronts per workgroup
     const dim3 gr((unsigned)a.ndm_total, (unsigned)std::max<int64_t>(1, std::min<int64_t>(
-                                             (nb + 15) / 16, 65535)));
+                                             (nb + 63) / 64, 65535)));
     const int ne = a.dered_elems;
     if (ne <= 4)
       hipLaunchKernelGGL(k_dered_base<4>, gr, dim3(256), 0, s, a);
