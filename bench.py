@@ -193,8 +193,10 @@ def robust_bench(sdd, torch, plan, xt, planes, out, ws, reps: int = 3):
 
 
 def ffa_levels(m: int, p: int):
-    """(LDS sub-stack depth d0, HBM passes) of the library's FFA schedule:
-    the shallowest depth whose sub-stacks hold <= 256 rows and <= 8192 bins."""
+    """Depth d0 of the library's LDS sub-stacks (the shallowest whose
+    sub-stacks hold <= 256 rows and <= 8192 bins): the levels above it run as
+    HBM passes, two levels per pass (one single-level pass first if d0 is
+    odd)."""
     fl = 0
     while (2 << fl) <= m:
         fl += 1
@@ -208,8 +210,8 @@ def ffa_bench(sdd, torch, plane, n_owned: int, reps: int = 3):
     """FFA folding + boxcar search of every trial of the step's plane (2048
     series of 2^18 samples) at base periods of 1024 and 128 samples.
     Algorithmic HBM bytes per folded sample: 4 (moments) + 4 + 4 (LDS levels:
-    read the rows, write the sub-stack profiles) + 12 per HBM pass (two
-    reads, one write) + 4 (boxcar read)."""
+    read the rows, write the sub-stack profiles) + 20 per two-level HBM pass
+    (four reads, one write) + 12 per single-level pass + 4 (boxcar read)."""
     import ctypes as C
     from paper_2605_03531_amd import _capi as A
     L = A.lib()
@@ -232,9 +234,10 @@ def ffa_bench(sdd, torch, plane, n_owned: int, reps: int = 3):
         t = ms.value / max(n.value, 1)
         d0 = ffa_levels(m, p)
         nel = series.shape[0] * m * p
-        by = nel * (16 + 12 * d0)
+        by = nel * (16 + 20 * (d0 // 2) + 12 * (d0 % 2))
         best, _, _ = out.host()
-        res[f"period_{p}"] = {"m": m, "hbm_passes": d0, "ms": round(t, 4),
+        res[f"period_{p}"] = {"m": m, "hbm_levels": d0, "hbm_passes": d0 // 2 + d0 % 2,
+                              "ms": round(t, 4),
                               "gsamples_per_s": round(nel / t / 1e6, 1),
                               "algorithmic_bytes": by, "gbps": round(by / t / 1e6, 1),
                               "max_snr": round(float(best["snr"].max()), 2)}

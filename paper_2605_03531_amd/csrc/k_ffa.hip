@@ -20,6 +20,7 @@
 // uint64: every sum is exact and every choice has a total order.
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "sdd_internal.h"
 
@@ -220,21 +221,36 @@ __global__ __launch_bounds__(kLdsThreads) void k_ffa_lds(FfaArgs a, int d0, int3
   for (int32_t e = threadIdx.x; e < ne; e += kLdsThreads) out[e] = A[e];
 }
 
-// Sources of every row at depths 0 .. d0-1 (the HBM passes), once per call.
+// Sources of every row for the HBM passes, once per call: entry (d, i) of
+// [d0][m] pairs of int4. A single level at depth d: {a, b, roll}; two levels
+// at depths d and d + 1 (rows at depth d + 2 in, depth d out):
+// out[i][j] = X[a1][j] + X[a2][j + ra] + X[b1][j + rb] + X[b2][j + rbb]
+// (indices mod p), {a1, a2, b1, b2}, {ra, rb, rbb, 0}. Depths below d0 have
+// no copies (every sub-stack there has two or more rows).
 __global__ __launch_bounds__(256) void k_ffa_table(int32_t m, int32_t p, int d0, int4* tab) {
   const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (k >= (int64_t)d0 * m) return;
   const int d = (int)(k / m);
   const int32_t i = (int32_t)(k - (int64_t)d * m);
-  int4 t;
-  ffa_sources(m, i, d, p, &t.x, &t.y, &t.z);
-  t.w = 0;
-  tab[k] = t;
+  int32_t a, b, r;
+  ffa_sources(m, i, d, p, &a, &b, &r);
+  int4 t0 = make_int4(a, b, r, 0), t1 = make_int4(0, 0, 0, 0);
+  if (d + 1 < d0) {
+    int32_t a1, a2, ra, b1, b2, rb;
+    ffa_sources(m, a, d + 1, p, &a1, &a2, &ra);
+    ffa_sources(m, b, d + 1, p, &b1, &b2, &rb);
+    t0 = make_int4(a1, a2, b1, b2);
+    t1 = make_int4(ra, r, (int32_t)(((int64_t)r + rb) % p), 0);
+  }
+  tab[2 * k] = t0;
+  tab[2 * k + 1] = t1;
 }
 
 // One upper level (depth d) through HBM: rows of src (series stride
 // src_pitch) to rows of dst; workgroup blockIdx.x of gridDim.x walks every
 // gridDim.x-th group of rows of series blockIdx.y.
+// TWO: levels d and d + 1 at once (four rows in, one out).
+template <bool TWO>
 __global__ __launch_bounds__(kThreads) void k_ffa_pass(FfaArgs a, int d, const uint32_t* src,
                                                        int64_t src_pitch, uint32_t* dst,
                                                        int64_t dst_pitch) {
@@ -244,13 +260,25 @@ __global__ __launch_bounds__(kThreads) void k_ffa_pass(FfaArgs a, int d, const u
   const uint32_t* s = src + (int64_t)sr * src_pitch;
   for (int32_t i = (int32_t)blockIdx.x * L.rstep + L.r0; i < a.m;
        i += (int32_t)gridDim.x * L.rstep) {
-    const int4 t = a.tab[(int64_t)d * a.m + i];
-    const int32_t ra = t.x, rb = t.y, sh = t.z;
-    const uint32_t* pa = s + (int64_t)ra * p;
+    const int4 t0 = a.tab[2 * ((int64_t)d * a.m + i)];
     uint32_t* po = dst + (int64_t)sr * dst_pitch + (int64_t)i * p;
-    if (rb < 0) {
-      for (int32_t j = L.j0; j < p; j += L.jstep) po[j] = pa[j];
+    if constexpr (TWO) {
+      const int4 t1 = a.tab[2 * ((int64_t)d * a.m + i) + 1];
+      const uint32_t* p0 = s + (int64_t)t0.x * p;
+      const uint32_t* p1 = s + (int64_t)t0.y * p;
+      const uint32_t* p2 = s + (int64_t)t0.z * p;
+      const uint32_t* p3 = s + (int64_t)t0.w * p;
+#pragma unroll 4
+      for (int32_t j = L.j0; j < p; j += L.jstep) {
+        int32_t k1 = j + t1.x, k2 = j + t1.y, k3 = j + t1.z;
+        if (k1 >= p) k1 -= p;
+        if (k2 >= p) k2 -= p;
+        if (k3 >= p) k3 -= p;
+        po[j] = p0[j] + p1[k1] + p2[k2] + p3[k3];
+      }
     } else {
+      const int32_t ra = t0.x, rb = t0.y, sh = t0.z;
+      const uint32_t* pa = s + (int64_t)ra * p;
       const uint32_t* pb = s + (int64_t)rb * p;
 #pragma unroll 4
       for (int32_t j = L.j0; j < p; j += L.jstep) {
@@ -486,12 +514,12 @@ int lds_depth(int64_t m, int32_t p) {
   return d0;
 }
 
-// moments [nseries] x 16 B, source tables [d0][m] x 16 B, two stacks
+// moments [nseries] x 16 B, source tables [d0][m] x 32 B, two stacks
 FfaLayout ffa_layout(int32_t nseries, int64_t m, int32_t p) {
   FfaLayout L;
   L.moments = 0;
   L.tab = round_up256((int64_t)nseries * 16);
-  int64_t off = L.tab + round_up256((int64_t)lds_depth(m, p) * m * 16);
+  int64_t off = L.tab + round_up256((int64_t)lds_depth(m, p) * m * 32);
   const int64_t stack = round_up256((int64_t)nseries * m * p * 4);
   L.buf0 = off;
   L.buf1 = off + stack;
@@ -582,7 +610,19 @@ extern "C" sdd_status sdd_ffa_search(int32_t device, const uint32_t* d_series, i
     if (k == nlev - 1 && d_profiles) return d_profiles;
     return bufs[k & 1];
   };
-  const int nlev = 1 + d0;  // the LDS kernel, then the passes at depths d0-1 .. 0
+  // the HBM levels d0-1 .. 0: one single-level pass first when d0 is odd,
+  // then passes of two levels each (the tables hold the matching entries)
+  struct Step {
+    int depth;  // depth of the rows the pass writes
+    bool two;
+  };
+  std::vector<Step> steps;
+  for (int dc = d0; dc > 0;) {
+    const bool two = !(dc == d0 && (d0 & 1));
+    steps.push_back({dc - (two ? 2 : 1), two});
+    dc -= two ? 2 : 1;
+  }
+  const int nlev = 1 + (int)steps.size();  // the LDS kernel, then the passes
   uint32_t* cur = dst_of(0, nlev);
   const int32_t cap = (int32_t)(height(d0) * period);
   const size_t lds_a = 2 * (size_t)cap * sizeof(uint32_t);
@@ -603,8 +643,13 @@ extern "C" sdd_status sdd_ffa_search(int32_t device, const uint32_t* d_series, i
                             (groups * per_grp) / (16 * kThreads) + 1}));
   for (int k = 1; k < nlev; ++k) {
     uint32_t* nxt = dst_of(k, nlev);
-    hipLaunchKernelGGL(k_ffa_pass, dim3((unsigned)gx_pass, (unsigned)nseries), dim3(kThreads), 0,
-                       s, a, d0 - k, cur, stack, nxt, stack);
+    const Step& st = steps[k - 1];
+    if (st.two)
+      hipLaunchKernelGGL(k_ffa_pass<true>, dim3((unsigned)gx_pass, (unsigned)nseries),
+                         dim3(kThreads), 0, s, a, st.depth, cur, stack, nxt, stack);
+    else
+      hipLaunchKernelGGL(k_ffa_pass<false>, dim3((unsigned)gx_pass, (unsigned)nseries),
+                         dim3(kThreads), 0, s, a, st.depth, cur, stack, nxt, stack);
     cur = nxt;
   }
   const int64_t gx_box = std::max<int64_t>(
