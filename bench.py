@@ -408,7 +408,7 @@ def main() -> int:
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: beams shard across GPUs with no exchange, so "
               "whole-job throughput at N GPUs is N independent copies of this run; "
-              "runs on more than one GPU are not part of this build.", file=sys.stderr)
+              "only the one-GPU run is measured.", file=sys.stderr)
         return 2
 
     import torch

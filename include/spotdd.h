@@ -416,8 +416,8 @@ sdd_status sdd_server_query(sdd_server* server, sdd_server_stats* out);
 /* Bandpass correction with time- and frequency-domain flagging of one chunk
  * (Section 2.1 and the paper's figure of its RFI tool), as exact integer
  * maps applied while the chunk is staged for dedispersion:
- *   m_c   mean of channel c over the unflagged samples (all in round 1), FP64
- *         of the exact integer sum;
+ *   m_c   mean of channel c over the unflagged samples (all samples in the
+ *         first round), FP64 of the exact integer sum;
  *   b_c   lower median of m over the median_window channels centred on c
  *         (clipped to the band): the bandpass;
  *   channel c flagged when |r_c - median(r)| > chan_sigma * 1.4826 * MAD(r),

@@ -75,7 +75,7 @@ def test_delay_invariants_tiny_and_full_band():
     assert d[0, 1] == 0 and d[0, 2] > d[0, 0] > d[0, 3] > 0
 
 
-def test_delay_survey_values_tiny():
+def test_delay_values_tiny():
     """The tiny workload: bottom channel at DM 100 is 2251 samples (Eq. (1)
     with the printed constant gives 2950.26 ms / 1.31072 ms = 2250.8) and the
     maximum delay at DM 200 is 4502."""
