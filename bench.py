@@ -35,6 +35,12 @@ WIDTHS = [1, 2, 4, 8, 16, 32, 64]
 # (v_pk_add_u16 / v_add3_u32), which is also one input byte per add from LDS
 # at 128 B/clk/CU
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 * 2 / 1e12
+# LDS bytes per add of the LDS-tiled kernel's interior stage for the tile shape
+# below (16 64-bit + 16 32-bit reads and 2 128-bit staging stores per wavefront
+# for 8192 adds), against the LDS rate a ds_read_b128 microbenchmark reached on
+# MI355X (237 B per clock per CU x 256 CUs x 2.4 GHz)
+LDS_BYTES_PER_ADD = {"tile": [1, 2, 8, 1, 8, 4], "bytes": (16 * 512 + 16 * 256 + 2 * 1024) / 8192}
+LDS_PEAK_TBPS = 237 * 256 * 2.4e9 / 1e12
 # HBM bytes of one dedispersion launch of this workload, from rocprofv3 FETCH_SIZE /
 # WRITE_SIZE scaled by a copy kernel of known size (profiles/k_dedisp_lds_full_band_hbm_bytes.md).
 # Valid for the tile shape it was taken with; any other shape reports null.
@@ -484,7 +490,13 @@ def main() -> int:
                      "peak": round(ALU_PEAK_TOPS, 1), "unit": "TOP/s",
                      "frac": round(achieved / ALU_PEAK_TOPS, 4),
                      "traffic": (MEASURED_TRAFFIC["bytes"]
-                                 if list(plan.get_tile(0)) == MEASURED_TRAFFIC["tile"] else None)},
+                                 if list(plan.get_tile(0)) == MEASURED_TRAFFIC["tile"] else None),
+                     "lds": ({"bytes_per_add": LDS_BYTES_PER_ADD["bytes"],
+                              "achieved": round(achieved * LDS_BYTES_PER_ADD["bytes"], 2),
+                              "peak": round(LDS_PEAK_TBPS, 1), "unit": "TB/s",
+                              "frac": round(achieved * LDS_BYTES_PER_ADD["bytes"] / LDS_PEAK_TBPS,
+                                            4)}
+                             if list(plan.get_tile(0)) == LDS_BYTES_PER_ADD["tile"] else None)},
         "cpu_baseline": None,
     }
     res["sift"] = sift_bench(sdd, torch, plan, out, float(w.dm_list[1] - w.dm_list[0]), 1 << 16)
