@@ -30,7 +30,7 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kLdsElems = 8192;  // u32 elements per LDS buffer of k_ffa_lds (two buffers)
 constexpr int kLdsRows = 256;    // rows of a sub-stack of k_ffa_lds
-constexpr int kLdsThreads = 512; // workgroup of k_ffa_lds
+constexpr int kLdsThreads = 1024; // workgroup of k_ffa_lds
 
 struct FfaArgs {
   const uint32_t* in;  // series s at in + s * in_pitch
