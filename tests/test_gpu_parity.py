@@ -163,6 +163,30 @@ def test_full_band_bench_config_sampled_rows():
     assert float(s["snr"].max()) > 7.0, (p, s)
 
 
+def test_multi_range_config_full_size_sampled_rows():
+    """The multi-range workload at full size: 4096 channels 750-550 MHz,
+    81.92 us, 2^19 owned samples, DM ranges 0-100/0.1, 100-300/0.2 (dec 2),
+    300-700/0.5 (dec 4), 700-1500/1 (dec 8), 1500-3000/2 (dec 16), widths
+    1..256: bit-exact plane rows and equal search results on the first,
+    middle and last trial of every range."""
+    widths = [1 << k for k in range(9)]
+    kw = dict(freqs_mhz=np.linspace(750.0, 550.0, 4096), t_samp=81.92e-6,
+              ranges=synth.MULTI_RANGES, widths=widths, cand_block=1024, threshold=7.0)
+    spec = oracle_plan(kw)
+    say("generating the multi-range input")
+    w = synth.multi_range(spec.overlap, delay_fn=oracle.delay_table)
+    plan = _make(kw, "time")
+    say("running the library")
+    ph, res, g = gpu_run(plan, w.x, time_major=True)
+    assert g["n_owned"] == 1 << 19
+    rows = [[0, len(r.dms) // 2, len(r.dms) - 1] for r in spec.ranges]
+    say(f"oracle on rows {rows}")
+    orc = oracle.run(spec, w.x, rows=rows)
+    compare_rows(spec, ph, orc)
+    rel = compare_search(spec, res, orc, full_rows=False)
+    say(f"multi-range full size: S/N rel err {rel:.2e}, {res[3]} candidates")
+
+
 def test_edge_single_channel_single_trial_minimum_length():
     kw = dict(freqs_mhz=[400.0], t_samp=1e-3, dm_list=[0.0], widths=[1], cand_block=1,
               threshold=0.5)
