@@ -14,8 +14,8 @@
 //   k_ffa_lds      the lowest levels: one workgroup per sub-stack that fits
 //                  in LDS (ping-pong), from the input rows to its profiles
 //   k_ffa_pass     one upper level through HBM: out[i] = A[a] + roll(A[b], sh)
-//   k_ffa_boxcar   one wavefront per profile: circular uint64 prefix sums in
-//                  LDS, each width's largest sum and first bin, FP64 S/N.
+//   k_ffa_boxcar   one segment of 16 or 64 lanes per profile: circular prefix
+//                  sums in LDS, each width's largest sum and first bin, FP64 S/N.
 // Profiles are uint32 (the host checks m * max_value < 2^32), boxcar sums
 // uint64: every sum is exact and every choice has a total order.
 #include <algorithm>
@@ -310,22 +310,28 @@ __device__ inline bool snr_better(double s, int32_t j, int32_t w, double s2, int
   return s > s2 || (s == s2 && (j < j2 || (j == j2 && w < w2)));
 }
 
-// Best (S/N, bin, width) of folded profiles: one wavefront per profile
-// (profiles 4 * blockIdx.x + wave + 4 * gridDim.x * k of series
-// blockIdx.y). Lane l sums its chunk of ceil(p / 64) consecutive bins; a
-// wave scan of the chunk sums gives P[k] = sum of bins < k in LDS (P[p] the
-// total), and the circular boxcar from bin j is P[j + w] - P[j], or
+// Best (S/N, bin, width) of folded profiles: one segment of W lanes per
+// profile (64 / W profiles per wavefront, so short profiles share a
+// wavefront's fixed costs); segment g of the workgroup takes profiles
+// g + G * gridDim.x * k of series blockIdx.y (G segments per workgroup).
+// Lane l of a segment sums its chunk of ceil(p / W) consecutive bins; a
+// segment scan of the chunk sums gives P[k] = sum of bins < k in LDS (P[p]
+// the total), and the circular boxcar from bin j is P[j + w] - P[j], or
 // P[p] - P[j] + P[j + w - p] past the end. Each lane keeps, per width, the
 // largest sum over its bins (first bin on ties: its bins ascend), turns it
 // into the FP64 S/N (B - w m mu) / (sigma sqrt(m w)) and keeps its best in
-// the search's order; one wave reduction in the same order ends the profile.
+// the search's order; one segment reduction in the same order ends the
+// profile. Shuffles never leave a segment, whose lanes share one profile.
+template <int W>
 __global__ __launch_bounds__(kThreads) void k_ffa_boxcar(FfaArgs a, const uint32_t* prof,
                                                          int64_t prof_pitch) {
-  extern __shared__ unsigned long long P_all[];  // 4 x (p + 1): u64 prefix or u32 p + w_max
+  // G x (p + 1) u64: per segment a u64 prefix, or a u32 prefix of p + w_max
+  extern __shared__ unsigned long long P_all[];
   __shared__ double wnum[SDD_MAX_WIDTHS], wden[SDD_MAX_WIDTHS];
+  constexpr int G = kThreads / W;  // segments per workgroup
   const int32_t p = a.p, sr = blockIdx.y;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  unsigned long long* P = P_all + (int64_t)wid * (p + 1);
+  const int lane = threadIdx.x % W, seg = threadIdx.x / W;
+  unsigned long long* P = P_all + (int64_t)seg * (p + 1);
   const uint64_t n = (uint64_t)a.m * (uint64_t)p;
   double mu, sigma;
   fold_mean_sigma(n, a.moments[2 * sr], a.moments[2 * sr + 1], &mu, &sigma);
@@ -335,15 +341,14 @@ __global__ __launch_bounds__(kThreads) void k_ffa_boxcar(FfaArgs a, const uint32
     wden[threadIdx.x] = sigma * sqrt((double)a.m * w);
   }
   __syncthreads();
-  // each wavefront loops on its own: no workgroup barrier below
-  for (int32_t s = (int32_t)blockIdx.x * (kThreads / 64) + wid; s < a.m;
-       s += (int32_t)gridDim.x * (kThreads / 64)) {
+  // each segment loops on its own: no workgroup barrier below
+  for (int32_t s = (int32_t)blockIdx.x * G + seg; s < a.m; s += (int32_t)gridDim.x * G) {
     const uint32_t* row = prof + (int64_t)sr * prof_pitch + (int64_t)s * p;
     // the previous profile's readers of P are done
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const int32_t c = (p + 63) / 64;
+    const int32_t c = (p + W - 1) / W;
     const int32_t k0 = min(lane * c, p), k1 = min(k0 + c, p);
     unsigned long long part = 0;
     uint32_t lmin = 0xffffffffu;
@@ -354,13 +359,13 @@ __global__ __launch_bounds__(kThreads) void k_ffa_boxcar(FfaArgs a, const uint32
       lmin = min(lmin, v);
     }
     unsigned long long inc = part;
-    for (int o = 1; o < 64; o <<= 1) {
-      const unsigned long long t = __shfl_up(inc, o, 64);
+    for (int o = 1; o < W; o <<= 1) {
+      const unsigned long long t = __shfl_up(inc, o, W);
       if (lane >= o) inc += t;
     }
-    for (int o = 32; o > 0; o >>= 1) lmin = min(lmin, (uint32_t)__shfl_xor((int)lmin, o, 64));
+    for (int o = W / 2; o > 0; o >>= 1) lmin = min(lmin, (uint32_t)__shfl_xor((int)lmin, o, W));
     const uint32_t base = lmin;  // the profile's smallest bin
-    const unsigned long long total = __shfl(inc, 63, 64);
+    const unsigned long long total = __shfl(inc, W - 1, W);
     // bins minus the smallest one: when their total fits 32 bits (the usual
     // case) the prefix of the offset bins is exact in uint32 and every boxcar
     // of them too; B = B' + w * base
@@ -380,7 +385,7 @@ __global__ __launch_bounds__(kThreads) void k_ffa_boxcar(FfaArgs a, const uint32
       // circular extension: Q[p + k] = Q[p] + Q[k]
       const uint32_t qtot = (uint32_t)(total - (unsigned long long)p * base);
       const int32_t wmax = a.widths[a.nwidths - 1];
-      for (int32_t k = lane; k < wmax; k += 64) Q[p + k] = qtot + Q[k];
+      for (int32_t k = lane; k < wmax; k += W) Q[p + k] = qtot + Q[k];
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -395,7 +400,7 @@ __global__ __launch_bounds__(kThreads) void k_ffa_boxcar(FfaArgs a, const uint32
             bb[u] = 0u;
             bjj[u] = -1;
           }
-          for (int32_t j = lane; j < p; j += 64) {
+          for (int32_t j = lane; j < p; j += W) {
             const uint32_t qj = Q[j];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
@@ -440,7 +445,7 @@ __global__ __launch_bounds__(kThreads) void k_ffa_boxcar(FfaArgs a, const uint32
           const int32_t w = a.widths[q];
           unsigned long long bb = 0ull;
           int32_t bjj = -1;
-          for (int32_t j = lane; j < p; j += 64) {
+          for (int32_t j = lane; j < p; j += W) {
             const int32_t e = j + w;
             const unsigned long long b = e <= p ? P[e] - P[j] : total - P[j] + P[e - p];
             if (bjj < 0 || b > bb) {
@@ -460,10 +465,10 @@ __global__ __launch_bounds__(kThreads) void k_ffa_boxcar(FfaArgs a, const uint32
       }
     }
     if (sigma > 0.0) {
-      for (int o = 32; o > 0; o >>= 1) {
-        const double s2 = __shfl_xor(bs, o, 64);
-        const int32_t j2 = __shfl_xor(bj, o, 64);
-        const int32_t w2 = __shfl_xor(bw, o, 64);
+      for (int o = W / 2; o > 0; o >>= 1) {
+        const double s2 = __shfl_xor(bs, o, W);
+        const int32_t j2 = __shfl_xor(bj, o, W);
+        const int32_t w2 = __shfl_xor(bw, o, W);
         if (snr_better(s2, j2, w2, bs, bj, bw)) {
           bs = s2;
           bj = j2;
@@ -626,12 +631,17 @@ extern "C" sdd_status sdd_ffa_search(int32_t device, const uint32_t* d_series, i
   uint32_t* cur = dst_of(0, nlev);
   const int32_t cap = (int32_t)(height(d0) * period);
   const size_t lds_a = 2 * (size_t)cap * sizeof(uint32_t);
-  const size_t lds_b = (size_t)(kThreads / 64) * (period + 1) * sizeof(unsigned long long);
+  // segment of W lanes per profile: profiles of up to 256 bins share a
+  // wavefront four at a time (measured: 2.8x faster at 128 bins; 32-lane
+  // segments were slower at 1024 bins than whole wavefronts)
+  const int wseg = period <= 256 ? 16 : 64;
+  const size_t lds_b = (size_t)(kThreads / wseg) * (period + 1) * sizeof(unsigned long long);
   // at most 64 KiB and 4 x 4097 x 8 bytes: within gfx950's 160 KiB per workgroup
   SDD_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ffa_lds),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 65536));
-  SDD_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ffa_boxcar),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_b));
+  const void* box = wseg == 16 ? reinterpret_cast<const void*>(&k_ffa_boxcar<16>)
+                               : reinterpret_cast<const void*>(&k_ffa_boxcar<64>);
+  SDD_HIP_TRY(hipFuncSetAttribute(box, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_b));
   hipLaunchKernelGGL(k_ffa_lds, dim3(1u << d0, (unsigned)nseries), dim3(kLdsThreads), lds_a, s,
                      a, d0, cap, cur, stack);
   // about 32K workgroups per pass, each with at least 16 elements per thread
@@ -652,10 +662,14 @@ extern "C" sdd_status sdd_ffa_search(int32_t device, const uint32_t* d_series, i
                          dim3(kThreads), 0, s, a, st.depth, cur, stack, nxt, stack);
     cur = nxt;
   }
+  const int64_t per_wg = kThreads / wseg;  // profiles in flight per workgroup
   const int64_t gx_box = std::max<int64_t>(
-      1, std::min<int64_t>((m + 3) / 4, (16384 + nseries - 1) / nseries));
-  hipLaunchKernelGGL(k_ffa_boxcar, dim3((unsigned)gx_box, (unsigned)nseries), dim3(kThreads),
-                     lds_b, s, a, cur, stack);
+      1, std::min<int64_t>((m + per_wg - 1) / per_wg, (16384 + nseries - 1) / nseries));
+  const dim3 gbox((unsigned)gx_box, (unsigned)nseries);
+  if (wseg == 16)
+    hipLaunchKernelGGL(k_ffa_boxcar<16>, gbox, dim3(kThreads), lds_b, s, a, cur, stack);
+  else
+    hipLaunchKernelGGL(k_ffa_boxcar<64>, gbox, dim3(kThreads), lds_b, s, a, cur, stack);
   SDD_HIP_TRY(hipGetLastError());
   return SDD_OK;
 }
