@@ -344,7 +344,8 @@ def serve_bench(sdd, torch, nbeams: int, sat_chunks: int, rt_periods: int, max_b
 def batch_bench(sdd, torch, nbeams: int):
     """nbeams beams of 4096 channels with owned lengths U[2^16, 2^18], 2048
     trials 0-1000, widths 1..64: per-beam dedisperse_search calls vs one
-    batch call (persistent multi-beam launch) vs its graph replay. Inputs are
+    batch call (persistent multi-beam launch) vs its graph replay vs the graph
+    replay of per-(beam, range) grid launches. Inputs are
     uniform random bytes made on the device (the integer path's timing does
     not depend on the values)."""
     import synth
@@ -387,6 +388,9 @@ def batch_bench(sdd, torch, nbeams: int):
     res["persistent_batch"] = {"seconds": round(t, 4), "value": round(units / t / 1e9, 2)}
     t = timed(lambda: batch.run(workspace=ws, graph=True, stream=side))
     res["graph_replay"] = {"seconds": round(t, 4), "value": round(units / t / 1e9, 2)}
+    # one grid launch per (beam, range), the whole batch captured and replayed as a HIP graph
+    t = timed(lambda: batch.run(workspace=ws, per_item=True, graph=True, stream=side))
+    res["per_item_graph_replay"] = {"seconds": round(t, 4), "value": round(units / t / 1e9, 2)}
     res["unit"] = UNIT
     log(f"batch: {res}")
     return res
