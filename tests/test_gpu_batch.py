@@ -80,3 +80,53 @@ def test_batch_modes_match_single_calls_and_oracle():
         ph = [single[k][0][0][:, :g["plane_cols"][0]].cpu().numpy().view(np.uint32)]
         compare_rows(spec, ph, orc)
         compare_search(spec, single[k][1], orc, full_rows=False)
+
+
+def test_batch_with_search_options_matches_single_calls():
+    """Robust statistics and de-reddening inside batches (persistent,
+    per-item and graph replays, replayed three times with eager work in
+    between) give the same bits as single calls; changing a plan's option
+    afterwards takes effect in the next replay."""
+    import torch
+    import paper_2605_03531_amd as sdd
+    beams = _beams()[:3]
+    opts = [("mad", (64, 2)), ("clip", None), ("moments", (128, 1))]
+    plans, xs, single = [], [], []
+    for (kw, spec, x), (st, dr) in zip(beams, opts):
+        plan = sdd.Plan(kw["freqs_mhz"], kw["t_samp"], dm_list=kw["dm_list"], widths=kw["widths"],
+                        cand_block=kw["cand_block"], threshold=kw["threshold"], layout="time")
+        plan.set_stats(st)
+        if dr is not None:
+            plan.set_dereddening(*dr)
+        xt = torch.from_numpy(synth.to_time_major(x)).to("cuda:0")
+        _, out = plan.dedisperse_search(xt)
+        torch.cuda.synchronize()
+        plans.append(plan)
+        xs.append(xt)
+        single.append(out.host())
+    for mode in ("persistent", "per_item", "graph"):
+        say(f"batch with search options, mode {mode}")
+        outs = [p.alloc_search_out() for p in plans]
+        batch = sdd.Batch([(p, x, None, o) for p, x, o in zip(plans, xs, outs)])
+        ws = batch.workspace()
+        side = torch.cuda.Stream()
+        for r in range(3 if mode == "graph" else 1):
+            for o in outs:
+                o.best.zero_()
+            torch.cuda.synchronize()
+            batch.run(workspace=ws, per_item=(mode == "per_item"), graph=(mode == "graph"),
+                      stream=side)
+            torch.cuda.synchronize()
+            for k in range(len(plans)):
+                h = outs[k].host()
+                assert h[0].tobytes() == single[k][0].tobytes(), (mode, r, k)
+                assert h[2].tobytes() == single[k][2].tobytes(), (mode, r, k)
+            _ = torch.ones(1 << 20, device="cuda:0").sum().item()
+    # an option changed after capture: the next replay uses it
+    plans[1].set_dereddening(64, 1)
+    _, ref = plans[1].dedisperse_search(xs[1])
+    outs = [p.alloc_search_out() for p in plans]
+    batch = sdd.Batch([(p, x, None, o) for p, x, o in zip(plans, xs, outs)])
+    batch.run(workspace=batch.workspace(), graph=True, stream=torch.cuda.Stream())
+    torch.cuda.synchronize()
+    assert outs[1].host()[0].tobytes() == ref.host()[0].tobytes()

@@ -82,3 +82,32 @@ def test_streamed_results_equal_one_shot_and_alone_equals_mix():
     for (tag, k), r in alone.items():
         assert r["best"].tobytes() == mix[(0, k)]["best"].tobytes()
         assert r["cands"].tobytes() == mix[(0, k)]["cands"].tobytes()
+
+
+def test_search_options_hold_in_the_server():
+    """Plans with robust statistics and de-reddening give the same results
+    streamed as in one-shot calls, and equal the oracle's."""
+    import torch
+    beams = [_beam(b, C) for b, C in enumerate([128, 256])]
+    plans = [_plan(kw) for kw, _, _ in beams]
+    plans[0].set_stats("mad")
+    plans[0].set_dereddening(64, 2)
+    plans[1].set_stats("clip", 3.0, 3)
+    opts = [(("mad",), (64, 2)), (("clip", 3.0, 3), None)]
+    say("serving 2 beams with search options")
+    mix = _serve(beams, plans, 21)
+    for b, (kw, spec, x) in enumerate(beams):
+        p = plans[b]
+        spec.stats, spec.dered = opts[b]
+        for k in range((CHUNKS * N - p.overlap) // N):
+            w = x[:, k * N:k * N + N + p.overlap]
+            xt = torch.from_numpy(synth.to_time_major(w)).to("cuda:0")
+            _, out = p.dedisperse_search(xt, cap=4096)
+            best, stats, cands, n = out.host()
+            r = mix[(b, k)]
+            assert r["status"] == 0 and r["ncand"] == n
+            assert r["best"].tobytes() == best.tobytes(), (b, k)
+            assert r["cands"].tobytes() == cands.tobytes(), (b, k)
+            if k == 1:
+                orc = oracle.run(spec, w, rows=[[0, len(kw["dm_list"]) // 2]])
+                compare_search(spec, (best, stats, cands, n), orc, full_rows=False)
