@@ -208,7 +208,10 @@ sdd_status sdd_plan_set_tile(sdd_plan* plan, int32_t range, const sdd_tile* tile
  *                        |y - mu| (exact selections).
  * sdd_dm_stats then reports this mu and sigma as mean and std (n, s1, s2
  * stay the plain moments). EINVAL on an unknown mode, or k <= 0 or iters
- * outside 1..64 for SDD_STATS_CLIPPED. */
+ * outside 1..64 for SDD_STATS_CLIPPED. Like sdd_plan_set_tile and
+ * sdd_plan_set_dereddening, it changes the plan for calls made afterwards
+ * (cached batch graphs are rebuilt); it must not run while another thread
+ * (or a server stream) is making calls with the plan. */
 enum { SDD_STATS_MOMENTS = 0, SDD_STATS_CLIPPED = 1, SDD_STATS_MEDIAN_MAD = 2 };
 sdd_status sdd_plan_set_stats(sdd_plan* plan, int32_t mode, double k, int32_t iters);
 /* Running-median de-reddening of every searched series (Section 3.3: the
