@@ -403,6 +403,24 @@ sdd_status sdd_stream_open(sdd_server* server, const sdd_plan* plan, int64_t chu
  * slot still holds samples of an unfinished output chunk: poll, then retry. */
 sdd_status sdd_stream_submit(sdd_stream* stream, const uint8_t* chunk, int64_t nsamp,
                              uint64_t seq, int32_t on_device);
+/* Checkpoint of a beam (resume after a restart or a move to another server):
+ * the next sequence number, the next output chunk not yet scheduled, and the
+ * spectra that chunk and the later ones still need (samples next_out * N ..
+ * submitted * N - 1, at most the ring). Output chunks already scheduled
+ * finish and are polled as usual and are not part of the checkpoint.
+ * host_out == NULL: *needed receives the size only; otherwise host_out must
+ * hold *needed bytes (SDD_ENOMEM if bytes is smaller). The caller must not
+ * submit to the stream during the call. The stream stays open. */
+sdd_status sdd_stream_snapshot(sdd_stream* stream, void* host_out, int64_t bytes,
+                               int64_t* needed);
+/* Opens a beam from a checkpoint: like sdd_stream_open with the checkpoint's
+ * chunk length, its ring refilled with the saved spectra; the next submit
+ * takes the saved next sequence number and the saved unscheduled output
+ * chunks are produced (bit for bit what the original stream would have
+ * produced). EINVAL if the checkpoint is malformed or does not fit the plan
+ * (channel count, overlap) or the ring; the sdd_stream_open errors otherwise. */
+sdd_status sdd_stream_restore(sdd_server* server, const sdd_plan* plan, const void* snapshot,
+                              int64_t bytes, uint64_t tag, sdd_stream** out);
 /* Stops the beam: no more submits, unscheduled output chunks are dropped,
  * scheduled ones finish (their results stay queued); frees the ring. */
 sdd_status sdd_stream_close(sdd_stream* stream);

@@ -139,6 +139,8 @@ _PROTOS = {
     "sdd_stream_footprint": (i32, [vp, vp, i64, C.POINTER(i64)]),
     "sdd_stream_open": (i32, [vp, vp, i64, u64, C.POINTER(vp)]),
     "sdd_stream_submit": (i32, [vp, vp, i64, u64, i32]),
+    "sdd_stream_snapshot": (i32, [vp, vp, i64, C.POINTER(i64)]),
+    "sdd_stream_restore": (i32, [vp, vp, vp, i64, u64, C.POINTER(vp)]),
     "sdd_stream_close": (i32, [vp]),
     "sdd_stream_poll": (i32, [vp, C.POINTER(Result), i32, i32, C.POINTER(i32)]),
     "sdd_result_release": (i32, [vp, C.POINTER(Result)]),

@@ -75,6 +75,7 @@ struct sdd_stream {
   std::map<int64_t, int64_t> done_flags;  // completed chunks above oldest_pending
   std::deque<std::pair<int64_t, int64_t>> submit_times;  // (seq, ns)
   bool closing = false;
+  bool frozen = false;        // a snapshot is reading the ring: schedule nothing
   int64_t ring_bytes = 0;
   int64_t item_ws = 0;        // workspace bytes of one of its chunks
 };
@@ -196,7 +197,7 @@ void scheduler(sdd_server* s) {
         bool any = false;
         for (size_t q = 0; q < ns && (int)batch.size() < s->d.max_batch; ++q) {
           sdd_stream* st = s->streams[(s->rr + q) % ns];
-          if (st->closing || !chunk_ready(st, st->next_out)) continue;
+          if (st->closing || st->frozen || !chunk_ready(st, st->next_out)) continue;
           batch.push_back(WorkItem{st, st->next_out, ready_time(st, st->next_out)});
           st->next_out++;
           st->inflight++;
@@ -485,6 +486,126 @@ extern "C" sdd_status sdd_stream_submit(sdd_stream* st, const uint8_t* chunk, in
   st->submit_times.emplace_back((int64_t)seq, now_ns());
   while (st->submit_times.size() > 64) st->submit_times.pop_front();
   s->cv_sched.notify_all();
+  return SDD_OK;
+}
+
+namespace {
+
+// Checkpoint of a stream: this header, then the spectra [count][nchan] of
+// samples first_sample .. first_sample + count - 1.
+struct SnapHeader {
+  uint64_t magic;
+  int32_t version, nchan;
+  int64_t N, O, submitted, next_out, first_sample, count;
+};
+constexpr uint64_t kSnapMagic = 0x3150414e53444453ull;  // "SDDSNAP1"
+
+// Copies samples [t0, t0 + n) between host memory and the ring rows they
+// occupy (t mod R), in at most two contiguous pieces.
+sdd_status ring_copy(sdd_stream* st, int64_t t0, int64_t n, uint8_t* host, bool to_host) {
+  const int64_t C = st->plan->nchan;
+  int64_t done = 0;
+  while (done < n) {
+    const int64_t r = (t0 + done) % st->R;
+    const int64_t piece = std::min(n - done, st->R - r);
+    uint8_t* dev = st->ring + r * C;
+    uint8_t* h = host + done * C;
+    if (to_host)
+      SDD_HIP_TRY(hipMemcpyAsync(h, dev, piece * C, hipMemcpyDeviceToHost, st->copy_stream));
+    else
+      SDD_HIP_TRY(hipMemcpyAsync(dev, h, piece * C, hipMemcpyHostToDevice, st->copy_stream));
+    done += piece;
+  }
+  SDD_HIP_TRY(hipStreamSynchronize(st->copy_stream));
+  return SDD_OK;
+}
+
+}  // namespace
+
+extern "C" sdd_status sdd_stream_snapshot(sdd_stream* st, void* host_out, int64_t bytes,
+                                          int64_t* needed) {
+  clear_error();
+  if (!st || !needed) SDD_FAIL(SDD_EINVAL, "null argument");
+  sdd_server* s = st->srv;
+  std::unique_lock<std::mutex> lk(s->mu);
+  if (st->closing) SDD_FAIL(SDD_ESTATE, "stream is closing");
+  // the oldest sample an output chunk not yet scheduled needs; output chunks
+  // already scheduled finish (and are polled) as usual
+  const int64_t first = st->next_out * st->N;
+  const int64_t count = std::max<int64_t>(0, st->submitted * st->N - first);
+  *needed = (int64_t)sizeof(SnapHeader) + count * st->plan->nchan;
+  if (!host_out) return SDD_OK;
+  if (bytes < *needed)
+    SDD_FAIL(SDD_ENOMEM, "snapshot needs %lld bytes", (long long)*needed);
+  st->frozen = true;  // the recorded next output chunk stays unscheduled while we read
+  SnapHeader h{};
+  h.magic = kSnapMagic;
+  h.version = 1;
+  h.nchan = st->plan->nchan;
+  h.N = st->N;
+  h.O = st->O;
+  h.submitted = st->submitted;
+  h.next_out = st->next_out;
+  h.first_sample = first;
+  h.count = count;
+  lk.unlock();
+  // submits of this stream come from its caller, not concurrently with this
+  // call, so the ring rows of [first, first + count) are stable
+  std::memcpy(host_out, &h, sizeof(h));
+  uint8_t* data = static_cast<uint8_t*>(host_out) + sizeof(h);
+  sdd_status rc = SDD_OK;
+  if (fake(s)) {
+    std::memset(data, 0, (size_t)(count * st->plan->nchan));
+  } else if (count > 0) {
+    DeviceGuard g(s->d.device);
+    rc = ring_copy(st, first, count, data, true);
+  }
+  lk.lock();
+  st->frozen = false;
+  s->cv_sched.notify_all();
+  return rc;
+}
+
+extern "C" sdd_status sdd_stream_restore(sdd_server* s, const sdd_plan* p, const void* snapshot,
+                                         int64_t bytes, uint64_t tag, sdd_stream** out) {
+  clear_error();
+  if (!s || !p || !snapshot || !out) SDD_FAIL(SDD_EINVAL, "null argument");
+  *out = nullptr;
+  SnapHeader h;
+  if (bytes < (int64_t)sizeof(h)) SDD_FAIL(SDD_EINVAL, "snapshot shorter than its header");
+  std::memcpy(&h, snapshot, sizeof(h));
+  if (h.magic != kSnapMagic || h.version != 1) SDD_FAIL(SDD_EINVAL, "not a stream snapshot");
+  if (h.nchan != p->nchan || h.O != p->overlap)
+    SDD_FAIL(SDD_EINVAL, "snapshot of %d channels and overlap %lld does not fit this plan",
+             h.nchan, (long long)h.O);
+  if (h.N < 1 || h.submitted < 0 || h.next_out < 0 || h.first_sample != h.next_out * h.N ||
+      h.count != std::max<int64_t>(0, h.submitted * h.N - h.first_sample) ||
+      bytes < (int64_t)sizeof(h) + h.count * h.nchan)
+    SDD_FAIL(SDD_EINVAL, "inconsistent snapshot");
+  sdd_stream* st = nullptr;
+  sdd_status rc = sdd_stream_open(s, p, h.N, tag, &st);
+  if (rc != SDD_OK) return rc;
+  if (h.count > st->R) {
+    sdd_stream_close(st);
+    SDD_FAIL(SDD_EINVAL, "snapshot holds more samples than the ring");
+  }
+  if (!fake(s) && h.count > 0) {
+    DeviceGuard g(s->d.device);
+    const uint8_t* data = static_cast<const uint8_t*>(snapshot) + sizeof(h);
+    rc = ring_copy(st, h.first_sample, h.count, const_cast<uint8_t*>(data), false);
+    if (rc != SDD_OK) {
+      sdd_stream_close(st);
+      return rc;
+    }
+  }
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    st->submitted = h.submitted;
+    st->next_out = h.next_out;
+    st->oldest_pending = h.next_out;
+    s->cv_sched.notify_all();
+  }
+  *out = st;
   return SDD_OK;
 }
 

@@ -487,13 +487,31 @@ class Batch:
 class Stream:
     """One beam of a Server (sdd_stream)."""
 
-    def __init__(self, server, plan, chunk_nsamp: int, tag: int):
+    def __init__(self, server, plan, chunk_nsamp: int, tag: int, snapshot: bytes = None):
         self.server, self.plan, self.n, self.tag = server, plan, int(chunk_nsamp), int(tag)
         h = C.c_void_p()
-        A.check(A.lib().sdd_stream_open(server.handle, plan.handle, self.n, self.tag,
-                                        C.byref(h)), "sdd_stream_open")
+        if snapshot is None:
+            A.check(A.lib().sdd_stream_open(server.handle, plan.handle, self.n, self.tag,
+                                            C.byref(h)), "sdd_stream_open")
+            self.seq = 0
+        else:
+            buf = C.create_string_buffer(bytes(snapshot), len(snapshot))
+            A.check(A.lib().sdd_stream_restore(server.handle, plan.handle, buf, len(snapshot),
+                                               self.tag, C.byref(h)), "sdd_stream_restore")
+            # header: magic u64, version i32, nchan i32, N, O, submitted (i64 each)
+            self.seq = int(np.frombuffer(bytes(snapshot)[32:40], dtype="<i8")[0])
         self._h = h
-        self.seq = 0
+
+    def snapshot(self) -> bytes:
+        """Checkpoint (sdd_stream_snapshot): the next sequence number, the next
+        unscheduled output chunk and the spectra it and later chunks need."""
+        need = C.c_int64()
+        A.check(A.lib().sdd_stream_snapshot(self._h, None, 0, C.byref(need)),
+                "sdd_stream_snapshot")
+        buf = C.create_string_buffer(need.value)
+        A.check(A.lib().sdd_stream_snapshot(self._h, buf, need.value, C.byref(need)),
+                "sdd_stream_snapshot")
+        return buf.raw[:need.value]
 
     def submit(self, chunk, seq: Optional[int] = None) -> int:
         """Copies chunk ([n][nchan] uint8 spectra: torch tensor on the device,
@@ -549,6 +567,11 @@ class Server:
 
     def open(self, plan, chunk_nsamp: int, tag: int = 0) -> Stream:
         return Stream(self, plan, chunk_nsamp, tag)
+
+    def restore(self, plan, snapshot: bytes, tag: int = 0) -> Stream:
+        """Opens a beam from a Stream.snapshot() checkpoint (sdd_stream_restore)."""
+        n = int(np.frombuffer(bytes(snapshot)[16:24], dtype="<i8")[0])
+        return Stream(self, plan, n, tag, snapshot=snapshot)
 
     def footprint(self, plan, chunk_nsamp: int) -> int:
         b = C.c_int64()

@@ -111,3 +111,56 @@ def test_search_options_hold_in_the_server():
             if k == 1:
                 orc = oracle.run(spec, w, rows=[[0, len(kw["dm_list"]) // 2]])
                 compare_search(spec, (best, stats, cands, n), orc, full_rows=False)
+
+
+def test_checkpoint_resume_on_another_server_is_bit_exact():
+    """A beam streamed for five chunks (its first output chunk comes from
+    this server), checkpointed, closed, and restored on a second server that
+    receives the remaining chunks: every output chunk, from either server,
+    equals the one-shot call on its window."""
+    import torch
+    import paper_2605_03531_amd as sdd
+    kw, spec, x = _beam(1, 256)
+    plan = _plan(kw)
+    xt = torch.from_numpy(synth.to_time_major(x)).to("cuda:0")
+    res = {}
+
+    def drain(srv, want):
+        t0 = time.time()
+        while len(res) < want and time.time() - t0 < 60:
+            for r in srv.poll(64, timeout_us=20000):
+                res[r["chunk"]] = r
+
+    srv = sdd.Server(hbm_budget=8 << 30, nstreams=2, max_batch=4, cap=4096)
+    s = srv.open(plan, N, tag=7)
+    K0 = 5
+    for k in range(K0):
+        while s.submit(xt[k * N:(k + 1) * N]) != 0:
+            drain(srv, len(res) + 1)
+    ready = max(0, (K0 * N - plan.overlap) // N)
+    assert ready >= 1
+    drain(srv, ready)
+    snap = s.snapshot()
+    s.close()
+    srv.close()
+    say(f"checkpoint after {K0} chunks: {len(snap)} bytes, {len(res)} results so far")
+    assert len(res) == ready
+    srv2 = sdd.Server(hbm_budget=8 << 30, nstreams=2, max_batch=4, cap=4096)
+    s2 = srv2.restore(plan, snap, tag=7)
+    assert s2.seq == K0
+    for k in range(K0, CHUNKS):
+        while s2.submit(xt[k * N:(k + 1) * N]) != 0:
+            drain(srv2, len(res) + 1)
+    total = (CHUNKS * N - plan.overlap) // N
+    drain(srv2, total)
+    srv2.close()
+    assert sorted(res) == list(range(total))
+    for k in range(total):
+        w = x[:, k * N:k * N + N + plan.overlap]
+        _, out = plan.dedisperse_search(torch.from_numpy(synth.to_time_major(w)).to("cuda:0"),
+                                        cap=4096)
+        best, stats, cands, n = out.host()
+        r = res[k]
+        assert r["status"] == 0 and r["ncand"] == n
+        assert r["best"].tobytes() == best.tobytes(), k
+        assert r["cands"].tobytes() == cands.tobytes(), k

@@ -133,3 +133,56 @@ def test_stream_rejects_channel_major_plans_and_bad_desc():
         sdd.Server(hbm_budget=0, fake_exec_us=10)
     with pytest.raises(sdd.SddError):
         sdd.Server(hbm_budget=1 << 30, nstreams=0, fake_exec_us=10)
+
+
+def test_snapshot_and_restore_resume_the_sequence():
+    """A checkpoint holds the next sequence number, the next unscheduled
+    output chunk and the spectra still needed; a stream restored from it
+    (on another server) continues the numbering and the output chunks, and
+    malformed or mismatched checkpoints are refused."""
+    import ctypes as C
+    p = _plan()
+    N = 1024
+    srv = sdd.Server(hbm_budget=1 << 40, nstreams=2, max_batch=4, fake_exec_us=500)
+    s = srv.open(p, N, tag=1)
+    got = []
+    for _ in range(4):
+        while s.submit(None) != 0:      # ring full: results first
+            got += srv.poll(64, timeout_us=2000)
+    ready = max(0, (4 * N - p.overlap) // N)
+    got += _drain(srv, ready - len(got))
+    assert sorted(r["chunk"] for r in got) == list(range(ready))
+    snap = s.snapshot()
+    h = np.frombuffer(snap[:64], dtype="<i8")
+    submitted, next_out, first, count = int(h[4]), int(h[5]), int(h[6]), int(h[7])
+    assert (submitted, next_out, first, count) == (4, ready, ready * N, (4 - ready) * N)
+    assert len(snap) == 64 + count * 64
+    s.close()
+    srv2 = sdd.Server(hbm_budget=1 << 40, nstreams=2, max_batch=4, fake_exec_us=500)
+    s2 = srv2.restore(p, snap, tag=2)
+    assert s2.seq == 4
+    with pytest.raises(sdd.SddError):
+        s2.submit(None, seq=3)          # the numbering continues at 4
+    got2 = []
+    for _ in range(3):
+        while s2.submit(None) != 0:
+            got2 += srv2.poll(64, timeout_us=2000)
+    more = max(0, (7 * N - p.overlap) // N) - ready
+    got2 += _drain(srv2, more - len(got2))
+    assert sorted(r["chunk"] for r in got2) == list(range(ready, ready + more))
+    assert all(r["tag"] == 2 for r in got2)
+    # refused: another channel count, a corrupted magic, a truncated buffer
+    L = A.lib()
+    h2 = C.c_void_p()
+    assert L.sdd_stream_restore(srv2.handle, _plan(nchan=32).handle, snap, len(snap), 3,
+                                C.byref(h2)) == A.SDD_EINVAL
+    bad = b"X" + snap[1:]
+    assert L.sdd_stream_restore(srv2.handle, p.handle, bad, len(bad), 3,
+                                C.byref(h2)) == A.SDD_EINVAL
+    assert L.sdd_stream_restore(srv2.handle, p.handle, snap, len(snap) - 1, 3,
+                                C.byref(h2)) == A.SDD_EINVAL
+    need = C.c_int64()
+    assert L.sdd_stream_snapshot(s2._h, None, 0, C.byref(need)) == A.SDD_OK
+    small = C.create_string_buffer(8)
+    assert L.sdd_stream_snapshot(s2._h, small, 8, C.byref(need)) == A.SDD_ENOMEM
+    s2.close()
