@@ -354,7 +354,7 @@ typedef struct sdd_server_desc {
   int32_t batch_flags;    /* SDD_BATCH_PER_ITEM (recommended) or 0 (persistent launch) */
   int32_t flags;          /* SDD_SERVER_FAKE */
   int32_t fake_exec_us;   /* batch duration in fake mode */
-  int32_t reserved;
+  int32_t fake_fail_every; /* fake mode: every n-th batch fails with SDD_EDEVICE (0: none) */
 } sdd_server_desc;
 
 /* One output chunk of one stream. best/cands are host memory owned by the

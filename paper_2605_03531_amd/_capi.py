@@ -86,7 +86,7 @@ SDD_SERVER_FAKE = 1
 class ServerDesc(C.Structure):
     _fields_ = [("hbm_budget", i64), ("device", i32), ("max_beams", i32), ("nstreams", i32),
                 ("max_batch", i32), ("ring_chunks", i32), ("cap", i32), ("batch_flags", i32),
-                ("flags", i32), ("fake_exec_us", i32), ("reserved", i32)]
+                ("flags", i32), ("fake_exec_us", i32), ("fake_fail_every", i32)]
 
 
 class Result(C.Structure):

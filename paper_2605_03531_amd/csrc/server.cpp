@@ -217,9 +217,15 @@ void scheduler(sdd_server* s) {
     slot->t_start = now_ns();
     s->batches++;
     s->chunks += (int64_t)batch.size();
+    const int64_t batch_no = s->batches;
     lk.unlock();
 
     sdd_status st = SDD_OK;
+    // fake mode: every fake_fail_every-th batch fails as a device error would
+    if (fake(s) && s->d.fake_fail_every > 0 && batch_no % s->d.fake_fail_every == 0) {
+      set_error("injected batch failure (batch %lld)", (long long)batch_no);
+      st = SDD_EDEVICE;
+    }
     if (!fake(s)) {
       std::vector<BatchJob> jobs(batch.size());
       slot->out_off.assign(batch.size(), 0);

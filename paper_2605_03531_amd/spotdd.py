@@ -543,7 +543,8 @@ class Server:
 
     def __init__(self, hbm_budget: int, device: int = 0, max_beams: int = 256,
                  nstreams: int = 2, max_batch: int = 8, ring_chunks: int = 2, cap: int = 1024,
-                 per_item: bool = True, fake_exec_us: Optional[int] = None):
+                 per_item: bool = True, fake_exec_us: Optional[int] = None,
+                 fake_fail_every: int = 0):
         d = A.ServerDesc()
         d.hbm_budget = int(hbm_budget)
         d.device = int(device)
@@ -556,6 +557,7 @@ class Server:
         if fake_exec_us is not None:
             d.flags = A.SDD_SERVER_FAKE
             d.fake_exec_us = int(fake_exec_us)
+            d.fake_fail_every = int(fake_fail_every)
         h = C.c_void_p()
         A.check(A.lib().sdd_server_create(C.byref(d), C.byref(h)), "sdd_server_create")
         self._h = h

@@ -186,3 +186,29 @@ def test_snapshot_and_restore_resume_the_sequence():
     small = C.create_string_buffer(8)
     assert L.sdd_stream_snapshot(s2._h, small, 8, C.byref(need)) == A.SDD_ENOMEM
     s2.close()
+
+
+def test_injected_batch_failures_are_reported_and_the_streams_go_on():
+    """A fake server whose every third batch fails as a device error would:
+    the failed output chunks come back with SDD_EDEVICE, every other chunk
+    with SDD_OK, each exactly once, and the beams keep streaming."""
+    p = _plan()
+    N = 1024
+    srv = sdd.Server(hbm_budget=1 << 40, nstreams=2, max_batch=2, fake_exec_us=300,
+                     fake_fail_every=3)
+    streams = [srv.open(p, N, tag=b) for b in range(3)]
+    got = []
+    for k in range(8):
+        for s in streams:
+            while s.submit(None) != 0:
+                got += srv.poll(64, timeout_us=2000)
+    per = (8 * N - p.overlap) // N
+    got += _drain(srv, 3 * per - len(got))
+    keys = [(r["tag"], r["chunk"]) for r in got]
+    assert sorted(keys) == sorted((b, k) for b in range(3) for k in range(per))
+    status = [r["status"] for r in got]
+    assert A.SDD_EDEVICE in status and A.SDD_OK in status
+    assert set(status) <= {A.SDD_OK, A.SDD_EDEVICE}
+    assert srv.stats()["batches"] >= 3
+    for s in streams:
+        s.close()
