@@ -74,7 +74,9 @@ int main() {
     sdd_result res[16];
     while (got.load() < want && !stop.load()) {
       int32_t n = 0;
-      if (sdd_stream_poll(srv, res, 16, 2000, &n) != SDD_OK) {
+      const sdd_status rc = sdd_stream_poll(srv, res, 16, 2000, &n);
+      if (rc == SDD_ETIMEDOUT) continue;  // nothing finished within 2 ms
+      if (rc != SDD_OK) {
         bad = true;
         return;
       }
