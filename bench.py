@@ -36,15 +36,17 @@ WIDTHS = [1, 2, 4, 8, 16, 32, 64]
 # at 128 B/clk/CU
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 * 2 / 1e12
 # LDS bytes per add of the LDS-tiled kernel's interior stage for the tile shape
-# below (16 64-bit + 16 32-bit reads and 2 128-bit staging stores per wavefront
-# for 8192 adds), against the LDS rate a ds_read_b128 microbenchmark reached on
-# MI355X (237 B per clock per CU x 256 CUs x 2.4 GHz)
-LDS_BYTES_PER_ADD = {"tile": [1, 2, 8, 1, 8, 4], "bytes": (16 * 512 + 16 * 256 + 2 * 1024) / 8192}
+# below (32 64-bit + 32 32-bit reads and at most 4 128-bit staging stores per
+# wavefront for 16384 adds: 8 channels x 2 trials x 1024 samples), against the
+# LDS rate a ds_read_b128 microbenchmark reached on MI355X (237 B per clock per
+# CU x 256 CUs x 2.4 GHz)
+LDS_BYTES_PER_ADD = {"tile": [1, 2, 8, 1, 8, 8],
+                     "bytes": (32 * 512 + 32 * 256 + 4 * 1024) / 16384}
 LDS_PEAK_TBPS = 237 * 256 * 2.4e9 / 1e12
 # HBM bytes of one dedispersion launch of this workload, from rocprofv3 FETCH_SIZE /
 # WRITE_SIZE scaled by a copy kernel of known size (profiles/k_dedisp_lds_full_band_hbm_bytes.md).
 # Valid for the tile shape it was taken with; any other shape reports null.
-MEASURED_TRAFFIC = {"tile": [1, 2, 8, 1, 8, 4], "bytes": 52.97e9}
+MEASURED_TRAFFIC = {"tile": [1, 2, 8, 1, 8, 8], "bytes": 52.85e9}
 
 
 def log(*a):

@@ -207,6 +207,79 @@ __device__ __forceinline__ void dd_tile_impl(const LdsArgs& a, int32_t dtile, in
   // entry k of the current stage, as a wave-uniform scalar
 #define SDD_WORD(k) __builtin_amdgcn_readlane(dcur[(k) / 64], (k) % 64)
 
+  // One group: channels cc, cc+1 of a stage, trial d of the wavefront. Its
+  // reads (12 bytes per chunk per channel) and v_perm selectors.
+  constexpr int NG = (CS / 2) * D;
+  struct Grp {
+    uint2 a01[M], b01[M];
+    uint32_t a2[M], b2[M];
+    uint32_t sA0, sB0;
+  };
+  auto fetch = [&](const uint8_t* bufp, const int32_t (&dcur)[NDV], int g, Grp& r) {
+    const int cc = 2 * (g / D), d = g % D;
+    const uint8_t* slotA = bufp + cc * slot;
+    const uint8_t* slotB = slotA + slot;
+    const uint32_t wA = (uint32_t)SDD_WORD(cc * D + d);
+    const uint32_t wB = (uint32_t)SDD_WORD((cc + 1) * D + d);
+    const int32_t adA = (int32_t)(wA & 0xfffffu);
+    const int32_t adB = (int32_t)(wB & 0xfffffu);
+    const uint32_t rA = wA >> 20, rB = wB >> 20;
+    // v_perm selectors: bytes r, r+1 (and r+2, r+3) into 16-bit fields for
+    // uint8 input; bytes r..r+3 in order for uint16 input
+    r.sA0 = ES == 1 ? 0x0c010c00u + rA * 0x00010001u : 0x03020100u + rA * 0x01010101u;
+    r.sB0 = ES == 1 ? 0x0c010c00u + rB * 0x00010001u : 0x03020100u + rB * 0x01010101u;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const uint8_t* pA = slotA + adA + 512 * m;
+      const uint8_t* pB = slotB + adB + 512 * m;
+      r.a01[m] = *reinterpret_cast<const uint2*>(pA);
+      r.b01[m] = *reinterpret_cast<const uint2*>(pB);
+      if constexpr (WIDE) {
+        const uint2 a23 = *reinterpret_cast<const uint2*>(pA + 8);
+        const uint2 b23 = *reinterpret_cast<const uint2*>(pB + 8);
+        // keep the full 64-bit reads (conflict-free at an 8-byte lane stride)
+        asm volatile("" ::"v"(a23.y), "v"(b23.y));
+        r.a2[m] = a23.x;
+        r.b2[m] = b23.x;
+      } else {
+        r.a2[m] = *reinterpret_cast<const uint32_t*>(pA + 8);
+        r.b2[m] = *reinterpret_cast<const uint32_t*>(pB + 8);
+      }
+    }
+  };
+  auto consume = [&](int g, const Grp& r) {
+    const int d = g % D;
+    const uint32_t sA0 = r.sA0, sB0 = r.sB0;
+    const uint32_t sA2 = sA0 + 0x00020002u;
+    const uint32_t sB2 = sB0 + 0x00020002u;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const uint2 a01 = r.a01[m], b01 = r.b01[m];
+      const uint32_t a2 = r.a2[m], b2 = r.b2[m];
+      if constexpr (ES == 1) {
+        acc[d][m][0] += __builtin_amdgcn_perm(a01.y, a01.x, sA0) +
+                        __builtin_amdgcn_perm(b01.y, b01.x, sB0);
+        acc[d][m][1] += __builtin_amdgcn_perm(a01.y, a01.x, sA2) +
+                        __builtin_amdgcn_perm(b01.y, b01.x, sB2);
+        acc[d][m][2] += __builtin_amdgcn_perm(a2, a01.y, sA0) +
+                        __builtin_amdgcn_perm(b2, b01.y, sB0);
+        acc[d][m][3] += __builtin_amdgcn_perm(a2, a01.y, sA2) +
+                        __builtin_amdgcn_perm(b2, b01.y, sB2);
+      } else {
+        // uint16 samples are already 16-bit fields: v_perm only aligns
+        acc[d][m][0] += __builtin_amdgcn_perm(a01.y, a01.x, sA0) +
+                        __builtin_amdgcn_perm(b01.y, b01.x, sB0);
+        acc[d][m][1] += __builtin_amdgcn_perm(a2, a01.y, sA0) +
+                        __builtin_amdgcn_perm(b2, b01.y, sB0);
+      }
+      // add this group into the accumulators now: left to itself the
+      // compiler keeps a group's widened words live to sum them with the
+      // next group's, which costs the registers the pipelining needs
+#pragma unroll
+      for (int k = 0; k < NPK; ++k) asm volatile("" : "+v"(acc[d][m][k]));
+    }
+  };
+
   const int32_t nstages = nchan / CS;  // whole stages
   const int32_t lane_off = 8 * lane + ES * TW * wt;  // bytes
   const int32_t fstages = (ES == 1 ? 256 : a.flush) / CS;
@@ -235,63 +308,15 @@ __device__ __forceinline__ void dd_tile_impl(const LdsArgs& a, int32_t dtile, in
       if (s + 2 < nstages) load_bases(s + 2, bnext);
     }
     const uint8_t* bufp = lds + (s & 1) * buf + lane_off;
+    // The stage's (channel pair, trial) groups are software-pipelined: the LDS
+    // reads of group g+1 are issued before group g is widened and added, so
+    // each wavefront has a group's reads in flight while it computes.
+    Grp gr[2];
+    fetch(bufp, dcur, 0, gr[0]);
 #pragma unroll
-    for (int cc = 0; cc < CS; cc += 2) {
-      const uint8_t* slotA = bufp + cc * slot;
-      const uint8_t* slotB = slotA + slot;
-#pragma unroll
-      for (int d = 0; d < D; ++d) {
-        const uint32_t wA = (uint32_t)SDD_WORD(cc * D + d);
-        const uint32_t wB = (uint32_t)SDD_WORD((cc + 1) * D + d);
-        const int32_t adA = (int32_t)(wA & 0xfffffu);
-        const int32_t adB = (int32_t)(wB & 0xfffffu);
-        const uint32_t rA = wA >> 20, rB = wB >> 20;
-        // v_perm selectors: bytes r, r+1 (and r+2, r+3) into 16-bit fields for
-        // uint8 input; bytes r..r+3 in order for uint16 input
-        const uint32_t sA0 = ES == 1 ? 0x0c010c00u + rA * 0x00010001u : 0x03020100u + rA * 0x01010101u;
-        const uint32_t sB0 = ES == 1 ? 0x0c010c00u + rB * 0x00010001u : 0x03020100u + rB * 0x01010101u;
-        const uint32_t sA2 = sA0 + 0x00020002u;
-        const uint32_t sB2 = sB0 + 0x00020002u;
-#pragma unroll
-        for (int m = 0; m < M; ++m) {
-          const uint8_t* pA = slotA + adA + 512 * m;
-          const uint8_t* pB = slotB + adB + 512 * m;
-          const uint2 a01 = *reinterpret_cast<const uint2*>(pA);
-          const uint2 b01 = *reinterpret_cast<const uint2*>(pB);
-          uint32_t a2, b2;
-          if constexpr (WIDE) {
-            const uint2 a23 = *reinterpret_cast<const uint2*>(pA + 8);
-            const uint2 b23 = *reinterpret_cast<const uint2*>(pB + 8);
-            // keep the full 64-bit reads (conflict-free at an 8-byte lane stride)
-            asm volatile("" ::"v"(a23.y), "v"(b23.y));
-            a2 = a23.x;
-            b2 = b23.x;
-          } else {
-            a2 = *reinterpret_cast<const uint32_t*>(pA + 8);
-            b2 = *reinterpret_cast<const uint32_t*>(pB + 8);
-          }
-          if constexpr (ES == 1) {
-            acc[d][m][0] += __builtin_amdgcn_perm(a01.y, a01.x, sA0) +
-                            __builtin_amdgcn_perm(b01.y, b01.x, sB0);
-            acc[d][m][1] += __builtin_amdgcn_perm(a01.y, a01.x, sA2) +
-                            __builtin_amdgcn_perm(b01.y, b01.x, sB2);
-            acc[d][m][2] += __builtin_amdgcn_perm(a2, a01.y, sA0) +
-                            __builtin_amdgcn_perm(b2, b01.y, sB0);
-            acc[d][m][3] += __builtin_amdgcn_perm(a2, a01.y, sA2) +
-                            __builtin_amdgcn_perm(b2, b01.y, sB2);
-          } else {
-            // uint16 samples are already 16-bit fields: v_perm only aligns
-            acc[d][m][0] += __builtin_amdgcn_perm(a01.y, a01.x, sA0) +
-                            __builtin_amdgcn_perm(b01.y, b01.x, sB0);
-            acc[d][m][1] += __builtin_amdgcn_perm(a2, a01.y, sA0) +
-                            __builtin_amdgcn_perm(b2, b01.y, sB0);
-          }
-        }
-      }
-      // keep the scheduler from hoisting the LDS reads of more than four
-      // channels at once (their registers would cost occupancy)
-      if constexpr (CS > 4)
-        if ((cc & 3) == 2) __builtin_amdgcn_sched_barrier(0);
+    for (int g = 0; g < NG; ++g) {
+      if (g + 1 < NG) fetch(bufp, dcur, g + 1, gr[(g + 1) & 1]);
+      consume(g, gr[g & 1]);
     }
     if (--fl == 0 || s + 1 == nstages) {
       flush();
@@ -439,11 +464,11 @@ hipError_t launch_one(const LdsArgs& a, hipStream_t s) {
 // The built menu, {D, M, WD, WT, CS, NLD, F}; sdd_tile carries it as
 // {kind 1 + F, D, WD, WT, pairs per lane = 4*M, CS}.
 #define SDD_LDS_SHAPES(X)      \
+  X(2, 2, 8, 1, 8, 2, 0)       \
   X(2, 2, 8, 1, 4, 1, 0)       \
   X(2, 2, 8, 1, 4, 1, 2)       \
   X(2, 2, 4, 1, 4, 2, 0)       \
   X(2, 2, 4, 1, 4, 2, 2)       \
-  X(2, 2, 8, 1, 8, 2, 0)       \
   X(2, 1, 4, 1, 4, 1, 0)       \
   X(4, 1, 4, 1, 4, 2, 0)       \
   X(4, 1, 4, 1, 4, 2, 2)       \
