@@ -27,6 +27,8 @@
 namespace sdd {
 namespace {
 
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
 // One DT x TT tile of one job. Every thread of the workgroup calls it; it
 // returns after a barrier, so the caller may reuse the LDS at once.
 // ES = input element bytes: 1 (uint8 rows) or 2 (uint16 rows of a decimated
@@ -106,8 +108,9 @@ __device__ __forceinline__ void dd_tile_impl(const LdsArgs& a, int32_t dtile, in
   const int64_t stage_drow = 4 * (int64_t)CS * ndm;  // delay-table bytes per stage
   static_assert(CS <= kDelayRowPad, "stage wider than the delay-table padding");
 
-  uint4 st[NLD];
-  uint32_t ext[NLD];
+  // copy 0 and copy 1 of each element as loaded (copy 1 is the same window
+  // 4 bytes on: a second 16-byte load from L1 costs no register moves)
+  u32x4 st0[NLD], st1[NLD];
   // d(c, i0) of each element's channel at a stage
   auto load_bases = [&](int32_t s, int32_t (&dst)[NLD]) {
     const uint8_t* row = ds + (int64_t)s * stage_drow;
@@ -123,8 +126,8 @@ __device__ __forceinline__ void dd_tile_impl(const LdsArgs& a, int32_t dtile, in
       const uint32_t off = eoff[k] + (uint32_t)(ES * (bases[k] & ~15));
       const uint8_t* src = row + off;
       if constexpr (INTERIOR) {
-        st[k] = *reinterpret_cast<const uint4*>(src);
-        ext[k] = *reinterpret_cast<const uint32_t*>(src + 16);
+        st0[k] = *reinterpret_cast<const u32x4*>(src);
+        st1[k] = *reinterpret_cast<const u32x4*>(src + 4);
       } else {
         // byte g of the row; zero past its end
         const int64_t g = ES * (t0 + (bases[k] & ~15)) + eq16[k];
@@ -137,8 +140,8 @@ __device__ __forceinline__ void dd_tile_impl(const LdsArgs& a, int32_t dtile, in
           for (int bb = 0; bb < 20; ++bb)
             if (g + bb < row_bytes) w[bb >> 2] |= (uint32_t)src[bb] << (8 * (bb & 3));
         }
-        st[k] = make_uint4(w[0], w[1], w[2], w[3]);
-        ext[k] = w[4];
+        st0[k] = u32x4{w[0], w[1], w[2], w[3]};
+        st1[k] = u32x4{w[1], w[2], w[3], w[4]};
       }
     }
   };
@@ -149,8 +152,8 @@ __device__ __forceinline__ void dd_tile_impl(const LdsArgs& a, int32_t dtile, in
       if (ecs[k] < CS) {
         uint8_t* c0 = base + elds[k];
         // copy 0 as loaded; copy 1 byte j = window byte j + 4
-        *reinterpret_cast<uint4*>(c0) = st[k];
-        *reinterpret_cast<uint4*>(c0 + win) = make_uint4(st[k].y, st[k].z, st[k].w, ext[k]);
+        *reinterpret_cast<u32x4*>(c0) = st0[k];
+        *reinterpret_cast<u32x4*>(c0 + win) = st1[k];
       }
     }
   };
@@ -170,13 +173,15 @@ __device__ __forceinline__ void dd_tile_impl(const LdsArgs& a, int32_t dtile, in
 
   // Read positions of a stage: lane k < CS*D holds entry k = slot*D + d,
   // trial d of this wavefront in that slot's channel, packed as bits 0-19 the
-  // LDS byte offset of its 8-byte word inside the slot (copy 1 when the
-  // offset within the word is >= 4) and bits 20-21 the remaining byte shift.
+  // LDS byte offset of its 8-byte word from the stage buffer (the slot's
+  // offset, plus copy 1 when the offset within the word is >= 4; at most
+  // CS * 2 * win < 80 KiB) and bits 20-21 the remaining byte shift.
   // They are computed here across the lanes, once per stage, so the compute
   // loop needs one v_readlane and a few scalar operations per channel and
   // trial, and no scalar-memory waits that would also drain its LDS reads.
   // A channel past nchan gets offset 0 into its all-zero window.
   uint32_t dl_off[NDV], dl_off0[NDV];  // bytes from the stage's first delay row
+  int32_t sl_off[NDV];                  // the entry's slot offset in the stage buffer
 #pragma unroll
   for (int v = 0; v < NDV; ++v) {
     const int32_t k = 64 * v + lane;
@@ -185,6 +190,7 @@ __device__ __forceinline__ void dd_tile_impl(const LdsArgs& a, int32_t dtile, in
     const int32_t csv = k < CS * D ? cs : 0;
     dl_off[v] = 4u * (uint32_t)(csv * ndm + (i < ndm ? i : ndm - 1));
     dl_off0[v] = 4u * (uint32_t)(csv * ndm + i0);
+    sl_off[v] = csv * slot;
   }
   int32_t rdv[NDV], rd0[NDV];
   auto load_words = [&](int32_t s) {
@@ -200,7 +206,7 @@ __device__ __forceinline__ void dd_tile_impl(const LdsArgs& a, int32_t dtile, in
     for (int v = 0; v < NDV; ++v) {
       const int32_t o = ES * (rdv[v] - (rd0[v] & ~15));
       const int32_t ad = (o & ~7) + ((o & 4) ? win : 0);
-      out[v] = ad | ((o & 3) << 20);
+      out[v] = (sl_off[v] + ad) | ((o & 3) << 20);
     }
   };
 
@@ -217,8 +223,6 @@ __device__ __forceinline__ void dd_tile_impl(const LdsArgs& a, int32_t dtile, in
   };
   auto fetch = [&](const uint8_t* bufp, const int32_t (&dcur)[NDV], int g, Grp& r) {
     const int cc = 2 * (g / D), d = g % D;
-    const uint8_t* slotA = bufp + cc * slot;
-    const uint8_t* slotB = slotA + slot;
     const uint32_t wA = (uint32_t)SDD_WORD(cc * D + d);
     const uint32_t wB = (uint32_t)SDD_WORD((cc + 1) * D + d);
     const int32_t adA = (int32_t)(wA & 0xfffffu);
@@ -230,8 +234,8 @@ __device__ __forceinline__ void dd_tile_impl(const LdsArgs& a, int32_t dtile, in
     r.sB0 = ES == 1 ? 0x0c010c00u + rB * 0x00010001u : 0x03020100u + rB * 0x01010101u;
 #pragma unroll
     for (int m = 0; m < M; ++m) {
-      const uint8_t* pA = slotA + adA + 512 * m;
-      const uint8_t* pB = slotB + adB + 512 * m;
+      const uint8_t* pA = bufp + adA + 512 * m;
+      const uint8_t* pB = bufp + adB + 512 * m;
       r.a01[m] = *reinterpret_cast<const uint2*>(pA);
       r.b01[m] = *reinterpret_cast<const uint2*>(pB);
       if constexpr (WIDE) {
