@@ -409,18 +409,34 @@ extern "C" sdd_status sdd_stream_open(sdd_server* s, const sdd_plan* p, int64_t 
   const int64_t ring_bytes = R * p->nchan;
   const int64_t out_bytes = result_bytes(p, s->d.cap);
   std::unique_lock<std::mutex> lk(s->mu);
-  if ((int32_t)s->streams.size() >= s->d.max_beams)
-    SDD_FAIL(SDD_EAGAIN, "server holds its maximum of %d beams", s->d.max_beams);
-  // admission by footprint: the ring, plus slot growth if this beam's chunks
-  // need more workspace or result space than the slots hold
-  int64_t grow = 0;
-  for (const auto& sl : s->slots) {
-    grow += std::max<int64_t>(0, slot_ws_bytes(s, iws) - sl.ws_cap);
-    grow += std::max<int64_t>(0, (int64_t)s->d.max_batch * out_bytes - sl.out_cap);
+  // Admission by footprint: the ring, plus slot growth if this beam's chunks
+  // need more workspace or result space than the slots hold. Slots are only
+  // resized while idle; waiting for that releases the lock, so every limit is
+  // checked again after each wait (another open may have taken the room).
+  // Nothing else releases the lock before the ring is counted in hbm_used.
+  for (;;) {
+    if ((int32_t)s->streams.size() >= s->d.max_beams)
+      SDD_FAIL(SDD_EAGAIN, "server holds its maximum of %d beams", s->d.max_beams);
+    int64_t grow = 0;
+    for (const auto& sl : s->slots) {
+      grow += std::max<int64_t>(0, slot_ws_bytes(s, iws) - sl.ws_cap);
+      grow += std::max<int64_t>(0, (int64_t)s->d.max_batch * out_bytes - sl.out_cap);
+    }
+    if (s->hbm_used + ring_bytes + grow > s->d.hbm_budget)
+      SDD_FAIL(SDD_EAGAIN, "beam needs %lld bytes; %lld of %lld in use",
+               (long long)(ring_bytes + grow), (long long)s->hbm_used,
+               (long long)s->d.hbm_budget);
+    if (grow == 0) break;
+    bool idle = true;
+    for (const auto& sl : s->slots) idle = idle && !sl.busy;
+    if (!idle) {
+      s->cv_done.wait(lk);
+      continue;
+    }
+    sdd_status gs = grow_slots_locked(s, iws, out_bytes);
+    if (gs != SDD_OK) return gs;
+    break;
   }
-  if (s->hbm_used + ring_bytes + grow > s->d.hbm_budget)
-    SDD_FAIL(SDD_EAGAIN, "beam needs %lld bytes; %lld of %lld in use", (long long)(ring_bytes + grow),
-             (long long)s->hbm_used, (long long)s->d.hbm_budget);
   auto st = std::make_unique<sdd_stream>();
   st->srv = s;
   st->plan = p;
@@ -430,16 +446,6 @@ extern "C" sdd_status sdd_stream_open(sdd_server* s, const sdd_plan* p, int64_t 
   st->R = R;
   st->ring_bytes = ring_bytes;
   st->item_ws = iws;
-  if (grow > 0) {
-    // slots are only resized while idle
-    s->cv_done.wait(lk, [&] {
-      for (const auto& sl : s->slots)
-        if (sl.busy) return false;
-      return true;
-    });
-    sdd_status gs = grow_slots_locked(s, iws, out_bytes);
-    if (gs != SDD_OK) return gs;
-  }
   if (!fake(s)) {
     DeviceGuard g(s->d.device);
     if (hipMalloc(&st->ring, ring_bytes) != hipSuccess)

@@ -212,3 +212,44 @@ def test_injected_batch_failures_are_reported_and_the_streams_go_on():
     assert srv.stats()["batches"] >= 3
     for s in streams:
         s.close()
+
+
+def test_concurrent_opens_cannot_overrun_the_budget():
+    """Two beams opened at once while a batch holds the only slot: both need
+    the slots grown, which waits for the slot; the budget fits one of them,
+    so exactly one open succeeds and the other gets SDD_EAGAIN (every limit is
+    checked again after the wait), and the server never counts more than its
+    budget."""
+    import threading
+    small, big = _plan(nchan=64), _plan(nchan=512)
+    N = 1024
+    probe = sdd.Server(hbm_budget=1 << 40, nstreams=1, max_batch=1, fake_exec_us=10)
+    probe.open(big, N)
+    used_big = probe.stats()["hbm_used"]        # slots sized for the big plan + its ring
+    ring_small = probe.footprint(small, N)
+    probe.close()
+    budget = used_big + ring_small
+    srv = sdd.Server(hbm_budget=budget, nstreams=1, max_batch=1, fake_exec_us=400000)
+    s = srv.open(small, N)
+    for _ in range((small.overlap + N - 1) // N + 1):
+        assert s.submit(None) == 0
+    time.sleep(0.05)                             # the one slot is now busy
+    out, gate = [], threading.Barrier(2)
+
+    def opener():
+        gate.wait()
+        try:
+            srv.open(big, N)
+            out.append(0)
+        except sdd.SddError as e:
+            out.append(e.status)
+
+    th = [threading.Thread(target=opener) for _ in range(2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join(10.0)
+    assert sorted(out) == sorted([0, A.SDD_EAGAIN])
+    st = srv.stats()
+    assert st["open_streams"] == 2 and st["hbm_used"] <= budget
+    srv.close()
