@@ -233,9 +233,10 @@ sdd_status sdd_plan_set_stats(sdd_plan* plan, int32_t mode, double k, int32_t it
 sdd_status sdd_plan_set_dereddening(sdd_plan* plan, int32_t block, int32_t half);
 /* Writes up to max menu entries to host_out; *n_out = menu size. */
 sdd_status sdd_tile_menu(sdd_tile* host_out, int32_t max, int32_t* n_out);
-/* Picks each 8-bit DM range's tile by timing every fitting menu shape on the
- * device with synthetic input of nsamp_in samples (enqueued on stream, then
- * synchronised). cache_path (may be NULL) is a text file of earlier choices
+/* Picks each DM range's tile by timing every fitting menu shape on the
+ * device with synthetic input of nsamp_in samples in the range's element
+ * type (uint8 rows, or uint16 rows of nsamp_in / dec samples for a decimated
+ * range; enqueued on stream, then synchronised). cache_path (may be NULL) is a text file of earlier choices
  * keyed by (nchan, ndm, decimation, delay spans, plane width): a hit skips the
  * timing, a miss appends the new choice. Allocates temporary device buffers
  * (input and one plane). Results never depend on the tile. */
@@ -335,6 +336,14 @@ sdd_status sdd_batch_dedisperse_search(const sdd_batch_item* items, int32_t n, i
 sdd_status sdd_batch_graph_clear(void);
 
 /* ---- streaming server (continuous batching of many beams) ---------------- */
+/* Section 2.2: beams arrive as blocks of spectra that a ring buffer of recent
+ * data holds long enough to absorb the pipeline's delay, and many beams are
+ * searched side by side. Here each beam's ring lives in device memory and
+ * keeps the max-delay overlap (plus the widest boxcar) between chunks, so
+ * output chunk k is the one-shot sdd_dedisperse_search of stream samples
+ * [kN, (k+1)N + O); ready chunks of all beams are batched onto the device
+ * as slots free up (continuous batching), and beams are admitted by their
+ * HBM footprint. */
 
 typedef struct sdd_server sdd_server;
 typedef struct sdd_stream sdd_stream;
@@ -372,6 +381,16 @@ typedef struct sdd_result {
   const sdd_candidate* cands;  /* [min(ncand, cap)] in (range, dm, sample) order */
   int64_t t_ready_ns, t_start_ns, t_done_ns;
   void* handle;
+  /* DM-time planes of the chunk, only for streams with sdd_stream_keep_planes
+   * on (nplanes = 0 otherwise): device memory owned by the server until
+   * sdd_result_release, range r as [plane_rows[r]][plane_pitch[r]] uint32
+   * (plane_rows[r] = the range's trials) with plane_cols[r] defined columns:
+   * the sdd_dedisperse plane of the same window of spectra. */
+  int32_t nplanes;
+  int32_t plane_rows[SDD_MAX_RANGES];
+  const uint32_t* d_planes[SDD_MAX_RANGES];
+  int64_t plane_pitch[SDD_MAX_RANGES];
+  int64_t plane_cols[SDD_MAX_RANGES];
 } sdd_result;
 
 typedef struct sdd_server_stats {
@@ -421,6 +440,21 @@ sdd_status sdd_stream_snapshot(sdd_stream* stream, void* host_out, int64_t bytes
  * (channel count, overlap) or the ring; the sdd_stream_open errors otherwise. */
 sdd_status sdd_stream_restore(sdd_server* server, const sdd_plan* plan, const void* snapshot,
                               int64_t bytes, uint64_t tag, sdd_stream** out);
+/* Plane retention for one beam (off by default). When on, each output chunk
+ * scheduled afterwards also writes its DM-time planes into a device buffer
+ * that the server allocates for that chunk (hipMalloc, outside the HBM
+ * budget: sum_r ndm_r * plane_pitch_r * 4 bytes) and frees at
+ * sdd_result_release; the result's d_planes describe it. A chunk whose buffer
+ * cannot be allocated comes back with SDD_ENOMEM. Meant for checking served
+ * planes against one-shot calls, not for the real-time loop: the allocation
+ * and the free (which waits for the device) sit on the serving path. */
+sdd_status sdd_stream_keep_planes(sdd_stream* stream, int32_t on);
+/* Copies a polled result's planes into caller buffers on `stream` (device
+ * to device; d_dst[r] rows of dst_pitch[r] >= plane_cols[r] elements).
+ * EINVAL if the result holds no planes. */
+sdd_status sdd_result_copy_planes(sdd_server* server, const sdd_result* result,
+                                  uint32_t* const* d_dst, const int64_t* dst_pitch,
+                                  void* stream);
 /* Stops the beam: no more submits, unscheduled output chunks are dropped,
  * scheduled ones finish (their results stay queued); frees the ring. */
 sdd_status sdd_stream_close(sdd_stream* stream);

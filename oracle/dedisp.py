@@ -49,7 +49,7 @@ __all__ = [
     "K_DM", "dm_range_values", "delay_table", "decimate", "corner_turn",
     "overlap_samples", "dedisperse", "dedisperse_rows", "row_moments",
     "mean_sigma", "boxcar_sums", "snr_matrix", "best_of", "search_row",
-    "PlanSpec", "RangeSpec", "make_plan", "run", "RowResult",
+    "PlanSpec", "RangeSpec", "make_plan", "run", "RowResult", "plane_checksums",
 ]
 
 K_DM = 4.148808e3  # s MHz^2 pc^-1 cm^3 (R1)
@@ -114,6 +114,36 @@ def dedisperse_rows(xr: np.ndarray, delays: np.ndarray, rows, length: int) -> np
             d = int(delays[i][c])
             y[k] += xr[c, d:d + length]
     return y
+
+
+def plane_checksums(xr: np.ndarray, delays: np.ndarray, length: int) -> Tuple[np.ndarray,
+                                                                             np.ndarray]:
+    """Two exact checksums of every row of the dedispersed plane, without
+    forming the plane: A[i] = sum_{j<length} y[i][j] and
+    B[i] = sum_{j<length} j * y[i][j], y as in dedisperse().
+
+    Each channel contributes the samples [d, d + length) of its row, d its
+    delay at trial i, so with per-channel prefix sums P[k] = sum_{t<k} x[t]
+    and Q[k] = sum_{t<k} t * x[t]:
+      A[i] = sum_c P[d + length] - P[d]
+      B[i] = sum_c (Q[d + length] - Q[d]) - d * (P[d + length] - P[d]).
+    int64 (exact while B stays below 2^63). Channels are taken one at a time
+    so memory stays at a few rows."""
+    xr = np.asarray(xr)
+    d = np.asarray(delays, dtype=np.int64)
+    ndm, nchan = d.shape
+    a = np.zeros(ndm, dtype=np.int64)
+    b = np.zeros(ndm, dtype=np.int64)
+    t = np.arange(xr.shape[1], dtype=np.int64)
+    for c in range(nchan):
+        row = xr[c].astype(np.int64)
+        p = np.concatenate(([0], np.cumsum(row)))
+        q = np.concatenate(([0], np.cumsum(row * t)))
+        lo, hi = d[:, c], d[:, c] + length
+        ps = p[hi] - p[lo]
+        a += ps
+        b += (q[hi] - q[lo]) - lo * ps
+    return a, b
 
 
 def row_moments(y: np.ndarray, n: int) -> Tuple[int, int]:

@@ -92,7 +92,10 @@ class ServerDesc(C.Structure):
 class Result(C.Structure):
     _fields_ = [("tag", u64), ("chunk", i64), ("status", i32), ("ncand", i32), ("ndm", i32),
                 ("reserved", i32), ("best", C.POINTER(DmBest)), ("cands", C.POINTER(Candidate)),
-                ("t_ready_ns", i64), ("t_start_ns", i64), ("t_done_ns", i64), ("handle", vp)]
+                ("t_ready_ns", i64), ("t_start_ns", i64), ("t_done_ns", i64), ("handle", vp),
+                ("nplanes", i32), ("plane_rows", i32 * SDD_MAX_RANGES),
+                ("d_planes", vp * SDD_MAX_RANGES),
+                ("plane_pitch", i64 * SDD_MAX_RANGES), ("plane_cols", i64 * SDD_MAX_RANGES)]
 
 
 class ServerStats(C.Structure):
@@ -144,6 +147,9 @@ _PROTOS = {
     "sdd_stream_close": (i32, [vp]),
     "sdd_stream_poll": (i32, [vp, C.POINTER(Result), i32, i32, C.POINTER(i32)]),
     "sdd_result_release": (i32, [vp, C.POINTER(Result)]),
+    "sdd_stream_keep_planes": (i32, [vp, i32]),
+    "sdd_result_copy_planes": (i32, [vp, C.POINTER(Result), C.POINTER(vp), C.POINTER(i64),
+                                     vp]),
     "sdd_server_query": (i32, [vp, C.POINTER(ServerStats)]),
     "sdd_rfi_workspace_size": (i32, [vp, i64, C.POINTER(i64)]),
     "sdd_rfi_estimate": (i32, [vp, vp, i64, i64, C.POINTER(RfiDesc), vp, vp, vp, vp, i64, vp]),

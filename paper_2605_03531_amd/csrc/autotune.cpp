@@ -1,6 +1,7 @@
 // Autotuner: for each DM range of a plan, times every tile shape of the built
-// menu that fits the range on the device (synthetic input) and keeps the
-// fastest. Results can be cached in a text file, one line per range shape:
+// menu that fits the range on the device (synthetic input in the range's own
+// element type: uint8 rows at decimation 1, uint16 sums of dec samples for a
+// decimated range) and keeps the fastest. Results can be cached in a text file, one line per range shape:
 //   <nchan> <ndm> <dec> <span32> <span64> <cols> <kind> <d> <wd> <wt> <ppl> <cs>
 // where span32/span64 are the range's delay spans over DM tiles of 32 and 64
 // trials and cols the plane width the tuning ran at.
@@ -59,15 +60,25 @@ void append_cache(const char* path, const Entry& e) {
   std::fclose(f);
 }
 
+__device__ __forceinline__ uint32_t hash32(int64_t i, uint32_t seed) {
+  uint32_t h = (uint32_t)i * 2654435761u ^ seed;
+  h ^= h >> 15;
+  h *= 2246822519u;
+  h ^= h >> 13;
+  return h;
+}
+
+// Synthetic rows: bytes, or uint16 values in [0, max_val] (a decimated
+// range's sums), so the timed kernel sees inputs of the range's own type.
 __global__ void k_fill_hash(uint8_t* p, int64_t n, uint32_t seed) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    uint32_t h = (uint32_t)i * 2654435761u ^ seed;
-    h ^= h >> 15;
-    h *= 2246822519u;
-    h ^= h >> 13;
-    p[i] = (uint8_t)h;
-  }
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = (uint8_t)hash32(i, seed);
+}
+__global__ void k_fill_hash16(uint16_t* p, int64_t n, uint32_t seed, uint32_t max_val) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = (uint16_t)(hash32(i, seed) % (max_val + 1u));
 }
 
 }  // namespace
@@ -98,7 +109,6 @@ extern "C" sdd_status sdd_autotune(sdd_plan* p, int64_t nsamp_in, const char* ca
   };
   for (size_t r = 0; r < p->ranges.size(); ++r) {
     Range& R = p->ranges[r];
-    if (R.dec != 1) continue;  // decimated ranges take the direct kernel
     const int64_t cols = cg.g.plane_cols[r];
     const Key key = range_key(p, (int32_t)r, cols);
     bool hit = false;
@@ -116,17 +126,36 @@ extern "C" sdd_status sdd_autotune(sdd_plan* p, int64_t nsamp_in, const char* ca
     clear_error();
     if (hit) continue;
     if (!x) {
-      const int64_t nx = (int64_t)p->nchan * nsamp_in;
+      // room for the uint8 rows and for any range's uint16 rows (pitch
+      // rounded to 128 samples as in the call workspace); the plane fits
+      // every range
+      int64_t row_bytes = nsamp_in;
+      for (const auto& RR : p->ranges)
+        if (RR.dec > 1)
+          row_bytes = std::max<int64_t>(row_bytes, 2 * ((nsamp_in / RR.dec + 127) / 128 * 128));
+      const int64_t nx = (int64_t)p->nchan * row_bytes;
       int64_t np = 0;
-      for (const auto& RR : p->ranges) np = std::max<int64_t>(np, (int64_t)RR.ndm());
-      np *= (cols + 63) / 64 * 64;
+      for (size_t q = 0; q < p->ranges.size(); ++q)
+        np = std::max<int64_t>(np, (int64_t)p->ranges[q].ndm() *
+                                       ((cg.g.plane_cols[q] + 63) / 64 * 64));
       if (hipMalloc(&x, nx) != hipSuccess || hipMalloc(&plane, np * 4) != hipSuccess ||
           hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
         cleanup();
         SDD_FAIL(SDD_ENOMEM, "autotune buffers do not fit");
       }
-      hipLaunchKernelGGL(k_fill_hash, dim3(4096), dim3(256), 0, s, x, nx, 12345u);
     }
+    // the range's input: uint8 rows, or uint16 rows of nsamp_in / dec samples
+    const int es = R.dec == 1 ? 1 : 2;
+    const int64_t xlen = nsamp_in / R.dec;
+    const int64_t xpitch = es == 1 ? nsamp_in : (xlen + 127) / 128 * 128;
+    if (cols + R.max_delay > xlen) continue;
+    if (es == 1)
+      hipLaunchKernelGGL(k_fill_hash, dim3(4096), dim3(256), 0, s, x,
+                         (int64_t)p->nchan * xpitch, 12345u);
+    else
+      hipLaunchKernelGGL(k_fill_hash16, dim3(4096), dim3(256), 0, s,
+                         reinterpret_cast<uint16_t*>(x), (int64_t)p->nchan * xpitch,
+                         12345u + (uint32_t)r, (uint32_t)(255 * R.dec));
     float best_ms = 1e30f;
     sdd_tile best = R.tile;
     int32_t best_span = R.tile_span;
@@ -135,16 +164,16 @@ extern "C" sdd_status sdd_autotune(sdd_plan* p, int64_t nsamp_in, const char* ca
       if (check_tile_fits(p, (int32_t)r, t, &span) != SDD_OK) continue;
       DedispArgs a{};
       a.x = x;
-      a.elem_bytes = 1;
-      a.x_pitch = nsamp_in;
-      a.x_len = nsamp_in;
+      a.elem_bytes = es;
+      a.x_pitch = xpitch;
+      a.x_len = xlen;
       a.nchan = p->nchan;
       a.delays = p->d_delays[r];
       a.ndm = R.ndm();
       a.plane = plane;
       a.plane_pitch = (cols + 63) / 64 * 64;
       a.cols = cols;
-      a.max_val = 255;
+      a.max_val = 255 * R.dec;
       a.tile = t;
       a.span = span;
       a.max_delay = R.max_delay;

@@ -26,6 +26,7 @@
 // scheduling, admission and backpressure logic is the same, so it can be
 // tested without a GPU.
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -51,12 +52,15 @@ struct WorkItem {
   sdd_stream* st;
   int64_t k;          // output chunk
   int64_t t_ready;
+  bool keep = false;  // write the planes into `planes` (a kept-planes stream)
+  uint8_t* planes = nullptr;  // device buffer of the chunk's planes, all ranges
 };
 
 struct ResultBox {
   sdd_result r{};
   std::vector<sdd_dm_best> best;
   std::vector<sdd_candidate> cands;
+  uint8_t* planes = nullptr;  // device memory behind r.d_planes (freed on release)
 };
 
 }  // namespace
@@ -76,6 +80,7 @@ struct sdd_stream {
   std::deque<std::pair<int64_t, int64_t>> submit_times;  // (seq, ns)
   bool closing = false;
   bool frozen = false;        // a snapshot is reading the ring: schedule nothing
+  bool keep_planes = false;   // output chunks also return their planes
   int64_t ring_bytes = 0;
   int64_t item_ws = 0;        // workspace bytes of one of its chunks
 };
@@ -122,6 +127,30 @@ bool fake(const sdd_server* s) { return (s->d.flags & SDD_SERVER_FAKE) != 0; }
 int64_t result_bytes(const sdd_plan* p, int32_t cap) {
   return align256((int64_t)p->ndm_total * sizeof(sdd_dm_best)) +
          align256((int64_t)cap * sizeof(sdd_candidate)) + 256;
+}
+
+// Plane layout of one output chunk (the workspace's plane pitches, ranges back
+// to back at 256-byte offsets); returns the bytes, or -1.
+int64_t chunk_planes(const sdd_plan* p, int64_t N, int64_t off[SDD_MAX_RANGES],
+                     int64_t pitch[SDD_MAX_RANGES], int64_t cols[SDD_MAX_RANGES]) {
+  CallGeom cg;
+  if (plan_geometry(p, N + p->overlap, &cg) != SDD_OK) return -1;
+  int64_t b = 0;
+  for (int r = 0; r < (int)p->ranges.size(); ++r) {
+    off[r] = b;
+    pitch[r] = cg.ws.plane_pitch[r];
+    cols[r] = cg.g.plane_cols[r];
+    b = align256(b + (int64_t)p->ranges[r].ndm() * pitch[r] * 4);
+  }
+  return b;
+}
+
+void free_box(sdd_server* s, ResultBox* b) {
+  if (b->planes && !fake(s)) {
+    DeviceGuard g(s->d.device);
+    (void)hipFree(b->planes);
+  }
+  delete b;
 }
 
 int64_t item_workspace(const sdd_plan* p, int64_t N) {
@@ -198,7 +227,8 @@ void scheduler(sdd_server* s) {
         for (size_t q = 0; q < ns && (int)batch.size() < s->d.max_batch; ++q) {
           sdd_stream* st = s->streams[(s->rr + q) % ns];
           if (st->closing || st->frozen || !chunk_ready(st, st->next_out)) continue;
-          batch.push_back(WorkItem{st, st->next_out, ready_time(st, st->next_out)});
+          batch.push_back(WorkItem{st, st->next_out, ready_time(st, st->next_out),
+                                   st->keep_planes && !fake(s), nullptr});
           st->next_out++;
           st->inflight++;
           any = true;
@@ -228,14 +258,36 @@ void scheduler(sdd_server* s) {
     }
     if (!fake(s)) {
       std::vector<BatchJob> jobs(batch.size());
+      // kept planes: one device buffer per chunk, handed to its result
+      std::vector<std::array<uint32_t*, SDD_MAX_RANGES>> pptr(batch.size());
+      std::vector<std::array<int64_t, SDD_MAX_RANGES>> ppitch(batch.size());
       slot->out_off.assign(batch.size(), 0);
       int64_t oo = 0;
+      for (size_t q = 0; q < batch.size() && st == SDD_OK; ++q) {
+        if (!slot->items[q].keep) continue;
+        const sdd_stream* bs = batch[q].st;
+        int64_t off[SDD_MAX_RANGES], cols[SDD_MAX_RANGES];
+        const int64_t bytes = chunk_planes(bs->plan, bs->N, off, ppitch[q].data(), cols);
+        void* buf = nullptr;
+        if (bytes <= 0 || hipMalloc(&buf, bytes) != hipSuccess) {
+          set_error("plane buffer of %lld bytes could not be allocated", (long long)bytes);
+          st = SDD_ENOMEM;
+          break;
+        }
+        slot->items[q].planes = static_cast<uint8_t*>(buf);
+        for (int r = 0; r < (int)bs->plan->ranges.size(); ++r)
+          pptr[q][r] = reinterpret_cast<uint32_t*>(slot->items[q].planes + off[r]);
+      }
       for (size_t q = 0; q < batch.size(); ++q) {
         const sdd_stream* bs = batch[q].st;
         const sdd_plan* p = bs->plan;
         BatchJob& j = jobs[q];
         std::memset(&j.it, 0, sizeof(j.it));
         j.it.plan = p;
+        if (slot->items[q].planes) {
+          j.it.d_planes = pptr[q].data();
+          j.it.plane_pitch = ppitch[q].data();
+        }
         j.it.d_in = bs->ring;
         j.it.nsamp_in = bs->N + bs->O;
         j.it.in_pitch = p->nchan;
@@ -254,7 +306,7 @@ void scheduler(sdd_server* s) {
       }
       std::vector<ItemGeom> geo;
       int64_t need = 0;
-      st = batch_layout(jobs.data(), (int32_t)jobs.size(), &geo, &need);
+      if (st == SDD_OK) st = batch_layout(jobs.data(), (int32_t)jobs.size(), &geo, &need);
       if (st == SDD_OK && need > slot->ws_cap) {
         set_error("internal: slot workspace %lld < %lld", (long long)slot->ws_cap,
                   (long long)need);
@@ -313,6 +365,16 @@ void completer(sdd_server* s) {
         std::memcpy(b->cands.data(), hc, sizeof(sdd_candidate) * b->cands.size());
       }
       sdd_result& r = b->r;
+      b->planes = w.planes;
+      if (w.planes && status == SDD_OK) {
+        int64_t off[SDD_MAX_RANGES];
+        chunk_planes(p, w.st->N, off, r.plane_pitch, r.plane_cols);
+        r.nplanes = (int32_t)p->ranges.size();
+        for (int q2 = 0; q2 < r.nplanes; ++q2) {
+          r.d_planes[q2] = reinterpret_cast<const uint32_t*>(w.planes + off[q2]);
+          r.plane_rows[q2] = p->ranges[q2].ndm();
+        }
+      }
       r.tag = w.st->tag;
       r.chunk = w.k;
       r.status = status;
@@ -669,9 +731,45 @@ extern "C" sdd_status sdd_result_release(sdd_server* s, sdd_result* r) {
   std::lock_guard<std::mutex> lk(s->mu);
   auto it = s->out_results.find(r->handle);
   if (it == s->out_results.end()) SDD_FAIL(SDD_EINVAL, "unknown or released result");
-  delete it->second;
+  ResultBox* b = it->second;
   s->out_results.erase(it);
   r->handle = nullptr;
+  free_box(s, b);
+  return SDD_OK;
+}
+
+extern "C" sdd_status sdd_stream_keep_planes(sdd_stream* st, int32_t on) {
+  clear_error();
+  if (!st) SDD_FAIL(SDD_EINVAL, "null argument");
+  std::lock_guard<std::mutex> lk(st->srv->mu);
+  st->keep_planes = on != 0;
+  return SDD_OK;
+}
+
+extern "C" sdd_status sdd_result_copy_planes(sdd_server* s, const sdd_result* r,
+                                             uint32_t* const* d_dst, const int64_t* dst_pitch,
+                                             void* stream) {
+  clear_error();
+  if (!s || !r || !r->handle || !d_dst || !dst_pitch) SDD_FAIL(SDD_EINVAL, "null argument");
+  const ResultBox* b = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->out_results.find(r->handle);
+    if (it == s->out_results.end()) SDD_FAIL(SDD_EINVAL, "unknown or released result");
+    b = it->second;
+  }
+  const sdd_result& br = b->r;
+  if (br.nplanes < 1) SDD_FAIL(SDD_EINVAL, "the result holds no planes");
+  for (int q = 0; q < br.nplanes; ++q)
+    if (!d_dst[q] || dst_pitch[q] < br.plane_cols[q])
+      SDD_FAIL(SDD_EINVAL, "range %d: destination pitch %lld < %lld columns", q,
+               (long long)dst_pitch[q], (long long)br.plane_cols[q]);
+  DeviceGuard g(s->d.device);
+  for (int q = 0; q < br.nplanes; ++q)
+    SDD_HIP_TRY(hipMemcpy2DAsync(d_dst[q], (size_t)dst_pitch[q] * 4, br.d_planes[q],
+                                 (size_t)br.plane_pitch[q] * 4, (size_t)br.plane_cols[q] * 4,
+                                 (size_t)br.plane_rows[q], hipMemcpyDeviceToDevice,
+                                 static_cast<hipStream_t>(stream)));
   return SDD_OK;
 }
 
@@ -707,8 +805,8 @@ extern "C" sdd_status sdd_server_destroy(sdd_server* s) {
   }
   s->th_sched.join();
   s->th_done.join();
-  for (ResultBox* b : s->results) delete b;
-  for (auto& kv : s->out_results) delete kv.second;
+  for (ResultBox* b : s->results) free_box(s, b);
+  for (auto& kv : s->out_results) free_box(s, kv.second);
   if (!fake(s)) {
     DeviceGuard g(s->d.device);
     for (auto& sl : s->slots) {

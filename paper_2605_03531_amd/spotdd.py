@@ -532,6 +532,13 @@ class Stream:
         self.seq = seq + 1
         return st
 
+    def keep_planes(self, on: bool = True) -> None:
+        """Output chunks scheduled from now on also return their DM-time
+        planes (sdd_stream_keep_planes); Server.poll copies them into device
+        tensors under the result's "planes"."""
+        A.check(A.lib().sdd_stream_keep_planes(self._h, int(bool(on))),
+                "sdd_stream_keep_planes")
+
     def close(self) -> None:
         if self._h is not None:
             A.check(A.lib().sdd_stream_close(self._h), "sdd_stream_close")
@@ -597,11 +604,33 @@ class Server:
             nc = min(r.ncand, self.cap)
             cands = np.frombuffer(C.string_at(r.cands, nc * CAND_DTYPE.itemsize) if nc else b"",
                                   dtype=CAND_DTYPE)
-            out.append({"tag": r.tag, "chunk": r.chunk, "status": r.status, "ncand": r.ncand,
-                        "best": best.copy(), "cands": cands.copy(), "t_ready_ns": r.t_ready_ns,
-                        "t_start_ns": r.t_start_ns, "t_done_ns": r.t_done_ns})
+            res = {"tag": r.tag, "chunk": r.chunk, "status": r.status, "ncand": r.ncand,
+                   "best": best.copy(), "cands": cands.copy(), "t_ready_ns": r.t_ready_ns,
+                   "t_start_ns": r.t_start_ns, "t_done_ns": r.t_done_ns}
+            if r.nplanes > 0:
+                res["planes"] = self._copy_planes(r)
+            out.append(res)
             A.check(A.lib().sdd_result_release(self._h, C.byref(r)), "sdd_result_release")
         return out
+
+    def _copy_planes(self, r) -> list:
+        """Device copies (int32 views of the uint32 sums, [ndm_r][plane_cols])
+        of a result's kept planes, made on the current stream and waited for."""
+        import torch
+        dst = []
+        ptrs = (C.c_void_p * A.SDD_MAX_RANGES)()
+        pitch = (C.c_int64 * A.SDD_MAX_RANGES)()
+        for q in range(r.nplanes):
+            t = torch.empty((int(r.plane_rows[q]), int(r.plane_cols[q])), dtype=torch.int32,
+                            device="cuda")
+            dst.append(t)
+            ptrs[q] = t.data_ptr()
+            pitch[q] = int(r.plane_cols[q])
+        s = torch.cuda.current_stream()
+        A.check(A.lib().sdd_result_copy_planes(self._h, C.byref(r), ptrs, pitch, s.cuda_stream),
+                "sdd_result_copy_planes")
+        s.synchronize()
+        return dst
 
     def stats(self) -> dict:
         s = A.ServerStats()

@@ -106,3 +106,69 @@ def compare_search(spec, res, orc, full_rows: bool):
         keys = [c[:3] for c in got]
         assert keys == sorted(keys)
     return max_rel
+
+
+def host_workers() -> int:
+    """Host threads for oracle work in the full-size tests (at most 16)."""
+    import os
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def oracle_rows_parallel(spec, x, rows, search=True):
+    """oracle.run(spec, x, rows) with the rows of each range shared among host
+    threads (numpy releases the GIL in the row additions). Same output
+    format: per range (rows, plane rows, RowResult list or None)."""
+    from concurrent.futures import ThreadPoolExecutor
+    assert spec.dered is None
+    owned = spec.owned(x.shape[1])
+    out = []
+    with ThreadPoolExecutor(host_workers()) as ex:
+        for r, rs in enumerate(spec.ranges):
+            rr = list(rows[r])
+            length = owned[r] + spec.w_max - 1
+            if not rr:
+                out.append((rr, np.zeros((0, length), dtype=np.int64), [] if search else None))
+                continue
+            xr = x if rs.dec == 1 else oracle.decimate(x, rs.dec)
+
+            def one(i, xr=xr, rs=rs, r=r, length=length):
+                y = oracle.dedisperse_rows(xr, rs.delays, [i], length)[0]
+                res = None
+                if search and spec.widths:
+                    res = oracle.search_row(y, spec.widths, owned[r], spec.cand_block,
+                                            spec.threshold, spec.stats)
+                return y, res
+
+            parts = list(ex.map(one, rr))
+            out.append((rr, np.stack([p[0] for p in parts]),
+                        [p[1] for p in parts] if search and spec.widths else None))
+    return out
+
+
+def oracle_checksums_parallel(xr, delays, length):
+    """oracle.plane_checksums over channel blocks in host threads, summed."""
+    from concurrent.futures import ThreadPoolExecutor
+    nchan = xr.shape[0]
+    step = max(1, -(-nchan // (4 * host_workers())))
+    blocks = [(c, min(nchan, c + step)) for c in range(0, nchan, step)]
+    with ThreadPoolExecutor(host_workers()) as ex:
+        parts = list(ex.map(lambda b: oracle.plane_checksums(xr[b[0]:b[1]],
+                                                             delays[:, b[0]:b[1]], length),
+                            blocks))
+    return sum(p[0] for p in parts), sum(p[1] for p in parts)
+
+
+def device_checksums(plane, cols):
+    """Row sums and index-weighted row sums of a device plane ([rows][pitch]
+    int32 view of uint32 sums below 2^31), int64 numpy."""
+    import torch
+    rows = plane.shape[0]
+    j = torch.arange(cols, device=plane.device, dtype=torch.int64)
+    a = torch.empty(rows, dtype=torch.int64, device=plane.device)
+    b = torch.empty(rows, dtype=torch.int64, device=plane.device)
+    for r0 in range(0, rows, 128):
+        blk = plane[r0:r0 + 128, :cols].to(torch.int64)
+        a[r0:r0 + 128] = blk.sum(dim=1)
+        b[r0:r0 + 128] = (blk * j).sum(dim=1)
+    torch.cuda.synchronize()
+    return a.cpu().numpy(), b.cpu().numpy()

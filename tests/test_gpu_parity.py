@@ -126,11 +126,64 @@ def test_multi_range_small_full_plane():
     assert n >= 3
 
 
-def test_full_band_bench_config_sampled_rows():
+def _pulse_rows(dms, pulses, ndm, reach=8):
+    """Rows within `reach` trials of each pulse's nearest trial (pulses whose
+    DM falls in this grid)."""
+    rows = set()
+    for p in pulses:
+        if dms[0] - 1 <= p.dm <= dms[-1] + 1:
+            k = int(np.argmin(np.abs(dms - p.dm)))
+            rows.update(range(max(0, k - reach), min(ndm, k + reach + 1)))
+    return rows
+
+
+def _run_full(plan, x, cap=1 << 20):
+    """Time-major upload, one call, planes kept on the device."""
+    import torch
+    xt = torch.from_numpy(synth.to_time_major(x)).to("cuda:0")
+    T = x.shape[1]
+    planes = plan.alloc_planes(T)
+    _, out = plan.dedisperse_search(xt, planes=planes, cap=cap)
+    torch.cuda.synchronize()
+    del xt
+    return planes, out.host(), plan.geometry(T)
+
+
+def _check_rows_and_checksums(spec, planes, res, g, x, rows, label):
+    """Bit-exact plane rows and search results on `rows` (per range), and the
+    row-sum / index-weighted row-sum checksums of every row of every plane
+    against the oracle's prefix-sum checksums."""
+    from _parity import device_checksums, oracle_checksums_parallel, oracle_rows_parallel
+    ph = []
+    for r in range(len(spec.ranges)):
+        idx = list(rows[r])
+        full = np.zeros((planes[r].shape[0], g["plane_cols"][r]), dtype=np.uint32)
+        if idx:
+            full[idx] = planes[r][idx, :g["plane_cols"][r]].cpu().numpy().view(np.uint32)
+        ph.append(full)
+    say(f"{label}: oracle on {sum(len(r) for r in rows)} rows")
+    orc = oracle_rows_parallel(spec, x, rows)
+    compare_rows(spec, ph, orc)
+    rel = compare_search(spec, res, orc, full_rows=False)
+    say(f"{label}: rows bit-exact, S/N rel err {rel:.2e}; checksums of every row")
+    for r, rs in enumerate(spec.ranges):
+        xr = x if rs.dec == 1 else oracle.decimate(x, rs.dec)
+        cols = g["plane_cols"][r]
+        ea, eb = oracle_checksums_parallel(xr, rs.delays, cols)
+        ga, gb = device_checksums(planes[r], cols)
+        bad = np.flatnonzero((ga != ea) | (gb != eb))
+        assert bad.size == 0, f"{label} range {r}: {bad.size} rows differ, first {bad[:8]}"
+    return orc
+
+
+@pytest.mark.timeout(900)
+def test_full_band_bench_config_rows_checksums_and_injections():
     """The benchmark's launch configuration at full size (4096 channels,
     2048 trials 0-1000, 2^18 owned samples, spectra input, widths 1..64):
-    bit-exact plane rows and search results on sampled trials, the DM-0 row
-    equal to the channel sum, and the brightest injected pulse found."""
+    bit-exact rows and search results on every trial within 8 of each
+    injected pulse's nearest trial, the edge trials and 32 seeded random
+    trials; exact row-sum and weighted row-sum checksums of all 2048 rows;
+    the DM-0 row equal to the channel sum; and injection recovery."""
     widths = [1, 2, 4, 8, 16, 32, 64]
     say("generating full-band input")
     w = synth.full_band(oracle.delay_table, widths=widths)
@@ -139,36 +192,59 @@ def test_full_band_bench_config_sampled_rows():
     plan = _make(kw, "time")
     spec = oracle_plan(kw)
     say("running the library")
-    ph, res, g = gpu_run(plan, w.x, time_major=True)
+    planes, res, g = _run_full(plan, w.x)
     assert g["n_owned"] == 1 << 18
     rng = np.random.Generator(np.random.PCG64(99))
-    rows = {0, 1, 1023, 2046, 2047}
+    rows = {0, 1, 1023, 2046, 2047} | _pulse_rows(w.dm_list, w.pulses, 2048)
+    rows.update(int(v) for v in rng.choice(2048, 32, replace=False))
+    rows = sorted(rows)
+    _check_rows_and_checksums(spec, planes, res, g, w.x, [rows], "full band")
+    col = w.x.sum(axis=0, dtype=np.int64)[: g["plane_cols"][0]]
+    assert (planes[0][0, :g["plane_cols"][0]].cpu().numpy().astype(np.int64) == col).all()
+    _injection_recovery(w, res)
+
+
+def _injection_recovery(w, res):
+    """Every injected pulse that should stand out is found: a candidate with
+    S/N above the threshold within 2 trials of the pulse's nearest trial,
+    whose window start lies where the pulse lands in that trial. The pulses
+    sit at off-grid DMs, so in trial k channel c puts the pulse at
+    t0 + d(c, DM) - d(c, DM_k): the pulse is smeared over the spread s of
+    those offsets and keeps about A * sqrt(w / (w + s)) of its matched S/N
+    A; pulses with A >= 10 whose smeared S/N stays >= 10 are required (the
+    boxcar widths are powers of two, so a little is lost to the mismatch)."""
+    cands = res[2]
+    found, need = 0, 0
     for p in w.pulses:
         k = int(np.argmin(np.abs(w.dm_list - p.dm)))
-        rows.update({k})
-    rows.update(int(v) for v in rng.integers(0, 2048, 4))
-    rows = sorted(rows)
-    say(f"oracle on {len(rows)} rows")
-    orc = oracle.run(spec, w.x, rows=[rows])
-    compare_rows(spec, ph, orc)
-    compare_search(spec, res, orc, full_rows=False)
-    col = w.x.sum(axis=0, dtype=np.int64)[: g["plane_cols"][0]]
-    assert (ph[0][0].astype(np.int64) == col).all()
-    # the brightest injected pulse stands out near its DM (off-grid DMs smear
-    # narrow pulses, so only the strongest one is required)
-    best = res[0]
-    p = max(w.pulses, key=lambda q: q.amp * np.sqrt(q.width))
-    k = int(np.argmin(np.abs(w.dm_list - p.dm)))
-    s = best[max(0, k - 3):k + 4]
-    assert float(s["snr"].max()) > 7.0, (p, s)
+        a = p.amp * np.sqrt(len(w.freqs_mhz) * p.width) / 16.0
+        dt = oracle.delay_table(w.freqs_mhz, [p.dm], w.t_samp)[0]
+        dk = oracle.delay_table(w.freqs_mhz, [w.dm_list[k]], w.t_samp)[0]
+        off = dt - dk
+        smeared = a * np.sqrt(p.width / (p.width + int(off.max() - off.min())))
+        if a < 10 or smeared < 10:
+            continue
+        need += 1
+        lo = p.t0 + int(off.min()) - 64
+        hi = p.t0 + int(off.max()) + p.width
+        hit = [c for c in cands if abs(int(c["dm_index"]) - k) <= 2
+               and lo <= int(c["sample"]) <= hi and float(c["snr"]) > 7.0]
+        say(f"pulse DM {p.dm:.2f} (trial {k}) width {p.width} A {a:.1f} smeared {smeared:.1f}: "
+            f"{len(hit)} candidates, best S/N {max([float(c['snr']) for c in hit] or [0]):.1f}")
+        assert hit, (p, k, lo, hi)
+        found += 1
+    assert need >= 5 and found == need
 
 
-def test_multi_range_config_full_size_sampled_rows():
+@pytest.mark.timeout(900)
+def test_multi_range_config_full_size_rows_and_checksums():
     """The multi-range workload at full size: 4096 channels 750-550 MHz,
     81.92 us, 2^19 owned samples, DM ranges 0-100/0.1, 100-300/0.2 (dec 2),
     300-700/0.5 (dec 4), 700-1500/1 (dec 8), 1500-3000/2 (dec 16), widths
-    1..256: bit-exact plane rows and equal search results on the first,
-    middle and last trial of every range."""
+    1..256: bit-exact rows and search results on every trial within 8 of an
+    injected pulse's nearest trial in its range, the first, middle and last
+    trial and 32 seeded random trials of every range; exact checksums of all
+    4350 rows."""
     widths = [1 << k for k in range(9)]
     kw = dict(freqs_mhz=np.linspace(750.0, 550.0, 4096), t_samp=81.92e-6,
               ranges=synth.MULTI_RANGES, widths=widths, cand_block=1024, threshold=7.0)
@@ -177,14 +253,17 @@ def test_multi_range_config_full_size_sampled_rows():
     w = synth.multi_range(spec.overlap, delay_fn=oracle.delay_table)
     plan = _make(kw, "time")
     say("running the library")
-    ph, res, g = gpu_run(plan, w.x, time_major=True)
+    planes, res, g = _run_full(plan, w.x)
     assert g["n_owned"] == 1 << 19
-    rows = [[0, len(r.dms) // 2, len(r.dms) - 1] for r in spec.ranges]
-    say(f"oracle on rows {rows}")
-    orc = oracle.run(spec, w.x, rows=rows)
-    compare_rows(spec, ph, orc)
-    rel = compare_search(spec, res, orc, full_rows=False)
-    say(f"multi-range full size: S/N rel err {rel:.2e}, {res[3]} candidates")
+    rng = np.random.Generator(np.random.PCG64(98))
+    rows = []
+    for rs in spec.ranges:
+        n = len(rs.dms)
+        sel = {0, n // 2, n - 1} | _pulse_rows(rs.dms, w.pulses, n)
+        sel.update(int(v) for v in rng.choice(n, 32, replace=False))
+        rows.append(sorted(sel))
+    _check_rows_and_checksums(spec, planes, res, g, w.x, rows, "multi-range")
+    say(f"multi-range full size: {res[3]} candidates")
 
 
 def test_edge_single_channel_single_trial_minimum_length():
@@ -308,3 +387,50 @@ def test_lds_tiles_on_channel_major_unaligned_input():
             continue
         ph, _, _ = gpu_run(plan, x, search=False)
         assert (ph[0].astype(np.int64) == yo).all(), tile
+
+
+def test_saturated_input_every_tile_grid_and_persistent():
+    """Inputs at the top of the sample range keep the packed 16-bit partial
+    sums at their bound: all-255 bytes (every plane value is the closed form
+    nchan * 255 * dec) and a seeded 0/255 mix (checked against the oracle),
+    523 channels (odd, not a multiple of any stage), a uint8 range and
+    decimated ranges whose uint16 samples reach 255 * dec (dec 2 and 16). Every
+    tile shape of the menu, as a grid launch and as the persistent multi-beam
+    launch, gives these exact planes."""
+    import paper_2605_03531_amd as sdd
+    f = np.linspace(750.0, 550.0, 523)
+    ranges = [(0.0, 20.0, 1.0, 1), (20.0, 40.0, 2.0, 2), (40.0, 80.0, 4.0, 16)]
+    kw = dict(freqs_mhz=f, t_samp=81.92e-6, ranges=ranges)
+    spec = oracle_plan(kw)
+    T = spec.overlap + 4 * 1024 + 16 * 7
+    rng = np.random.Generator(np.random.PCG64(255))
+    inputs = {"all255": np.full((523, T), 255, dtype=np.uint8),
+              "mix0_255": (rng.integers(0, 2, (523, T)) * 255).astype(np.uint8)}
+    expect = {"all255": None, "mix0_255": oracle.run(spec, inputs["mix0_255"], search=False)}
+    plan = _make(kw, "time")
+    ran = 0
+    for tile in _menu_tiles():
+        try:
+            plan.set_tile(tile)
+        except Exception:
+            continue
+        ran += 1
+        for name, x in inputs.items():
+            say(f"saturated input {name}, tile {tile}")
+            import torch
+            xt = torch.from_numpy(synth.to_time_major(x)).to("cuda:0")
+            g = plan.geometry(T)
+            grid = plan.dedisperse(xt)
+            batch_planes = plan.alloc_planes(T)
+            for pl in batch_planes:
+                pl.fill_(-1)
+            sdd.Batch([(plan, xt, batch_planes, None)]).run()
+            torch.cuda.synchronize()
+            for form, planes in (("grid", grid), ("persistent", batch_planes)):
+                ph = [sdd.plane_host(planes[r], g["plane_cols"][r]) for r in range(3)]
+                if expect[name] is None:
+                    for r, rs in enumerate(spec.ranges):
+                        assert (ph[r] == 523 * 255 * rs.dec).all(), (form, tile, r)
+                else:
+                    compare_rows(spec, ph, expect[name])
+    assert ran >= 3

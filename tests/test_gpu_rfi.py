@@ -112,3 +112,26 @@ def test_estimate_then_search_finds_the_pulse():
     assert k == 100 and int(best[k]["sample"]) == 3000 and int(best[k]["width"]) == 4
     fl = flags.cpu().numpy()
     assert fl[30] and fl[31] and fl[200]
+
+
+@pytest.mark.parametrize("rounds", [1, 2])
+def test_rfi_hand_worked_case_on_the_device(rounds):
+    """The hand-worked 7 x 10 case of the oracle's pins (3-channel median
+    window): round 1 flags channels {2, 5} and sample {4}; round 2 flags
+    channel {5} and sample {4} (means over the kept samples, zero-DM series
+    over the round's own channels)."""
+    import torch
+    import sys
+    import os
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from test_oracle_rfi import hand_case
+    x = hand_case()
+    plan, _ = _plan(7, "chan")
+    lut, mask, flags = plan.rfi_estimate(torch.from_numpy(x).to("cuda:0"), median_window=3,
+                                         rounds=rounds)
+    torch.cuda.synchronize()
+    want_c = [2, 5] if rounds == 1 else [5]
+    assert np.nonzero(flags.cpu().numpy())[0].tolist() == want_c
+    assert np.nonzero(mask.cpu().numpy() == 0)[0].tolist() == [4]
+    _, _, _, olut, _ = oracle.rfi_estimate(x, window=3, rounds=rounds)
+    assert np.array_equal(lut.cpu().numpy(), olut)

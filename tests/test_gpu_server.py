@@ -164,3 +164,73 @@ def test_checkpoint_resume_on_another_server_is_bit_exact():
         assert r["status"] == 0 and r["ncand"] == n
         assert r["best"].tobytes() == best.tobytes(), k
         assert r["cands"].tobytes() == cands.tobytes(), k
+
+
+@pytest.mark.timeout(600)
+def test_serving_config_shape_planes_bit_exact():
+    """The serving workload's shape: beams of 1024, 2048 and 4096 channels
+    (750-550 MHz, 81.92 us), 2^16-sample chunks, 2048 trials 0-1000, widths
+    1..64, overlap kept in each beam's device ring. With plane retention on,
+    every served output chunk's plane equals the one-shot plane of the same
+    window of spectra bit for bit, its per-trial best values and candidates
+    are identical, and the oracle matches two rows per beam (plane and
+    search) on output chunk 1."""
+    import torch
+    import paper_2605_03531_amd as sdd
+    Nc = 1 << 16
+    widths = [1, 2, 4, 8, 16, 32, 64]
+    dms = np.linspace(0.0, 1000.0, 2048)
+    beams = []
+    for b, C in enumerate(synth.stream_beam_params(3)):
+        f = np.linspace(750.0, 550.0, C)
+        kw = dict(freqs_mhz=f, t_samp=81.92e-6, dm_list=dms, widths=widths, cand_block=1024,
+                  threshold=7.0)
+        spec = oracle_plan(kw)
+        T = 4 * Nc
+        say(f"serving shape: beam {b}, {C} channels, overlap {spec.overlap}")
+        x = synth.filterbank(700 + b, C, T, 128.0, 16.0)
+        d = oracle.delay_table(f, [300.0 + 200.0 * b], 81.92e-6)
+        synth.inject_pulse(x, d[0], Nc + 5000 + 1000 * b, 8, 3.0)
+        beams.append((kw, spec, x))
+    plans = [_plan(kw) for kw, _, _ in beams]
+    srv = sdd.Server(hbm_budget=64 << 30, nstreams=2, max_batch=4, cap=4096)
+    xs = [torch.from_numpy(synth.to_time_major(x)).to("cuda:0") for _, _, x in beams]
+    streams = [srv.open(p, Nc, tag=b) for b, p in enumerate(plans)]
+    for s in streams:
+        s.keep_planes(True)
+    res = []
+    for k in range(4):
+        for b, s in enumerate(streams):
+            while s.submit(xs[b][k * Nc:(k + 1) * Nc]) != 0:
+                res += srv.poll(16, timeout_us=10000)
+    want = sum((4 * Nc - p.overlap) // Nc for p in plans)
+    t0 = time.time()
+    while len(res) < want and time.time() - t0 < 120:
+        res += srv.poll(16, timeout_us=20000)
+    srv.close()
+    assert len(res) == want == 6
+    got = {(r["tag"], r["chunk"]): r for r in res}
+    for b, (kw, spec, x) in enumerate(beams):
+        p = plans[b]
+        for k in range((4 * Nc - p.overlap) // Nc):
+            r = got[(b, k)]
+            assert r["status"] == 0 and len(r["planes"]) == 1
+            w = x[:, k * Nc:k * Nc + Nc + p.overlap]
+            xt = torch.from_numpy(synth.to_time_major(w)).to("cuda:0")
+            one = p.alloc_planes(w.shape[1])
+            _, out = p.dedisperse_search(xt, planes=one, cap=4096)
+            best, stats, cands, n = out.host()
+            cols = p.geometry(w.shape[1])["plane_cols"][0]
+            assert r["planes"][0].shape == (2048, cols)
+            assert torch.equal(r["planes"][0], one[0][:, :cols]), (b, k)
+            assert r["ncand"] == n and r["best"].tobytes() == best.tobytes(), (b, k)
+            assert r["cands"].tobytes() == cands.tobytes(), (b, k)
+            if k == 1:
+                kp = int(np.argmin(np.abs(dms - (300.0 + 200.0 * b))))
+                rows = [0, kp]
+                orc = oracle.run(spec, w, rows=[rows])
+                yo = orc[0][1]
+                assert (r["planes"][0][rows].cpu().numpy().astype(np.int64) == yo).all()
+                compare_search(spec, (best, stats, cands, n), orc, full_rows=False)
+            say(f"beam {b} chunk {k}: served plane == one-shot plane, {n} candidates")
+            del r["planes"], one, xt

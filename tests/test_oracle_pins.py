@@ -344,3 +344,33 @@ def test_tiny_workload_recovers_injected_pulse():
     assert rows[k] == 100
     assert res[k].best[1:] == (3000, 4)
     assert res[k].best[0] > 20.0
+
+
+def test_plane_checksums_equal_brute_force_sums():
+    """The prefix-sum checksums of every plane row equal the row sum and the
+    index-weighted row sum of the explicit per-sample triple loop (catches an
+    off-by-one in the prefix bounds, a missing delay term in the weighted sum
+    or a transposed delay table); uint16 rows of a decimated range too."""
+    rng = _rng(17)
+    for nchan, T, ndm, hi in [(1, 30, 1, 255), (7, 150, 6, 255), (16, 300, 9, 4080)]:
+        f = np.sort(rng.uniform(300, 500, nchan))[::-1]
+        dms = np.sort(rng.uniform(0, 12, ndm))
+        d = oracle.delay_table(f, dms, 5e-3)
+        L = T - int(d.max())
+        x = rng.integers(0, hi + 1, (nchan, T)).astype(np.uint8 if hi == 255 else np.uint16)
+        y = _brute(x, d, L)
+        a, b = oracle.plane_checksums(x, d, L)
+        j = np.arange(L)
+        assert a.tolist() == [int(sum(int(v) for v in row)) for row in y]
+        assert b.tolist() == [int(sum(int(k) * int(v) for k, v in zip(j, row))) for row in y]
+
+
+def test_plane_checksums_closed_form_constant_input():
+    """Constant input v: every row is nchan*v over `length` samples, so the
+    checksums are nchan*v*L and nchan*v*L*(L-1)/2 at every trial."""
+    f = np.linspace(750, 550, 33)
+    d = oracle.delay_table(f, np.linspace(0, 40, 11), 81.92e-6)
+    L = 5000
+    x = np.full((33, L + int(d.max())), 201, dtype=np.uint8)
+    a, b = oracle.plane_checksums(x, d, L)
+    assert (a == 33 * 201 * L).all() and (b == 33 * 201 * L * (L - 1) // 2).all()
