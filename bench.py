@@ -47,6 +47,9 @@ LDS_PEAK_TBPS = 237 * 256 * 2.4e9 / 1e12
 # WRITE_SIZE scaled by a copy kernel of known size (profiles/k_dedisp_lds_full_band_hbm_bytes.md).
 # Valid for the tile shape it was taken with; any other shape reports null.
 MEASURED_TRAFFIC = {"tile": [1, 2, 8, 1, 8, 8], "bytes": 61.13e9}
+# Adds per VALU instruction of the dedispersion kernel for that tile, from the
+# SQ counters (profiles/k_dedisp_lds_full_band_sq_counters.md)
+ADDS_PER_VALU = {"tile": [1, 2, 8, 1, 8, 8], "adds": 66.3}
 
 
 def log(*a):
@@ -64,25 +67,72 @@ def cpu_model() -> str:
     return platform.processor() or "unknown"
 
 
-def cpu_baseline(w, plan_delays, rows: int):
-    """The oracle as it stands, on `rows` DM trials of the same input and
-    owned length (dedispersion + search), one host core."""
+def _oracle_rows(w, d, sel, cols, n_owned, threads: int) -> float:
+    """Wall seconds for the oracle (dedispersion + boxcar search) of the DM
+    rows `sel`, shared among `threads` host threads (numpy releases the GIL
+    in the row additions)."""
+    from concurrent.futures import ThreadPoolExecutor
     import oracle
+
+    def one(k):
+        y = oracle.dedisperse(w.x, d[k:k + 1], cols)
+        oracle.search_row(y[0], WIDTHS, n_owned, 1024, 7.0)
+
+    t0 = time.perf_counter()
+    if threads == 1:
+        for k in range(len(sel)):
+            one(k)
+    else:
+        with ThreadPoolExecutor(threads) as ex:
+            list(ex.map(one, range(len(sel))))
+    return time.perf_counter() - t0
+
+
+def host_threads() -> int:
+    """Host threads for the oracle's all-core timing: the CPU share of one
+    GPU on the box (at most 16), or fewer if the host has fewer."""
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def cpu_baseline(w, plan_delays, rows: int):
+    """The oracle as it stands, on a bounded sample of DM trials of the same
+    input and owned length (dedispersion + search), timed on one host thread
+    (as the paper's single-thread CPU baseline) and on all of the host's
+    threads; plus the tiny workload timed in full."""
+    import oracle
+    import synth
     n_owned = w.nsamp - (int(plan_delays.max()) + max(WIDTHS) - 1)
     cols = n_owned + max(WIDTHS) - 1
-    sel = np.linspace(0, len(w.dm_list) - 1, rows).astype(int)
-    d = oracle.delay_table(w.freqs_mhz, w.dm_list[sel], w.t_samp)
+    nth = host_threads()
+    sel1 = np.linspace(0, len(w.dm_list) - 1, rows).astype(int)
+    d1 = oracle.delay_table(w.freqs_mhz, w.dm_list[sel1], w.t_samp)
+    dt1 = _oracle_rows(w, d1, sel1, cols, n_owned, 1)
+    seln = np.linspace(0, len(w.dm_list) - 1, rows * max(1, nth // 2)).astype(int)
+    dn = oracle.delay_table(w.freqs_mhz, w.dm_list[seln], w.t_samp)
+    dtn = _oracle_rows(w, dn, seln, cols, n_owned, nth)
+    v1 = w.nchan * len(sel1) * n_owned / dt1 / 1e9
+    vn = w.nchan * len(seln) * n_owned / dtn / 1e9
+    # the tiny workload (256 channels, 201 trials, 8192 samples), in full
+    t = synth.tiny(oracle.delay_table)
+    spec = oracle.make_plan(t.freqs_mhz, t.t_samp, dm_list=t.dm_list, widths=t.widths,
+                            cand_block=t.cand_block, threshold=t.threshold)
     t0 = time.perf_counter()
-    y = oracle.dedisperse(w.x, d, cols)
-    for k in range(rows):
-        oracle.search_row(y[k], WIDTHS, n_owned, 1024, 7.0)
-    dt = time.perf_counter() - t0
-    units = w.nchan * rows * n_owned
-    return {"value": units / dt / 1e9, "unit": UNIT, "cores": 1, "kind": "oracle",
-            "sample": f"{rows} of {len(w.dm_list)} DM trials (evenly spaced), full 4096 channels "
-                      f"x {n_owned} owned samples, dedispersion + boxcar search, numpy FP64/int64 "
-                      f"oracle, {dt:.1f} s on 1 thread of {cpu_model()} "
-                      f"({os.cpu_count()} logical CPUs)"}
+    oracle.run(spec, t.x)
+    dtt = time.perf_counter() - t0
+    n_t = spec.owned(t.nsamp)[0]
+    model = cpu_model()
+    return {"value": round(v1, 4), "unit": UNIT, "cores": 1, "kind": "oracle",
+            "sample": f"{len(sel1)} of {len(w.dm_list)} DM trials (evenly spaced), full 4096 "
+                      f"channels x {n_owned} owned samples, dedispersion + boxcar search, numpy "
+                      f"FP64/int64 oracle, {dt1:.1f} s on 1 thread of {model} "
+                      f"({os.cpu_count()} logical CPUs); the metric is linear in the trials",
+            "all_cores": {"value": round(vn, 4), "unit": UNIT, "cores": nth,
+                          "sample": f"{len(seln)} DM trials shared among {nth} host threads, "
+                                    f"{dtn:.1f} s"},
+            "tiny_full": {"value": round(256 * 201 * n_t / dtt / 1e9, 4), "unit": UNIT,
+                          "cores": 1, "seconds": round(dtt, 3),
+                          "sample": "tiny workload in full: 256 channels x 201 trials x "
+                                    f"{n_t} samples, dedispersion + search of every trial"}}
 
 
 # Candidate sifting measured after the step: stencils of (1, 4) DM steps x (16, 128) samples,
@@ -343,6 +393,111 @@ def serve_bench(sdd, torch, nbeams: int, sat_chunks: int, rt_periods: int, max_b
     return out
 
 
+def probe_ceilings():
+    """VALU and LDS rates of this GPU from the ceiling probe built with the
+    library (paper_2605_03531_amd/probe/ceilings.hip), or None."""
+    exe = os.path.join(ROOT, "paper_2605_03531_amd", "probe", "sdd_ceilings")
+    try:
+        r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+        if r.returncode == 0:
+            return json.loads(r.stdout.strip().splitlines()[-1])
+        log(f"ceiling probe failed: {r.stderr.strip()[-300:]}")
+    except (OSError, subprocess.TimeoutExpired, ValueError) as e:
+        log(f"ceiling probe not run: {e}")
+    return None
+
+
+def normal_u8_device(torch, rows: int, cols: int, mean: float, std: float, seed: int):
+    """Seeded clip(round(N(mean, std)), 0, 255) bytes made on the device in
+    row blocks (the integer path's timing does not depend on the values)."""
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(seed)
+    x = torch.empty((rows, cols), dtype=torch.uint8, device="cuda:0")
+    for r0 in range(0, rows, 1 << 16):
+        r1 = min(rows, r0 + (1 << 16))
+        v = torch.randn((r1 - r0, cols), generator=gen, device="cuda:0") * std + mean
+        x[r0:r1] = v.round_().clamp_(0, 255).to(torch.uint8)
+        del v
+    return x
+
+
+def multi_range_bench(sdd, torch, steps: int, warmup: int):
+    """The multi-range workload: 4096 channels 750-550 MHz, 81.92 us,
+    2^19 owned samples + overlap, five DM ranges (0-100/0.1 dec 1,
+    100-300/0.2 dec 2, 300-700/0.5 dec 4, 700-1500/1 dec 8, 1500-3000/2
+    dec 16), boxcar widths 1..256, threshold 7; spectra input N(128, 16).
+    One step = corner turn, decimation, five planes, search. Throughput in
+    each range's own samples (sum_r C ndm_r N_r) and at the native rate
+    (C ndm N); HBM roofline lines of the corner turn and the decimation."""
+    import ctypes as C
+    import synth
+    from paper_2605_03531_amd import _capi as A
+    L = A.lib()
+    widths = [1 << k for k in range(9)]
+    f = np.linspace(750.0, 550.0, 4096)
+    plan = sdd.Plan(f, 81.92e-6, ranges=synth.MULTI_RANGES, widths=widths, cand_block=1024,
+                    threshold=7.0, layout="time")
+    T = (1 << 19) + plan.overlap
+    g = plan.geometry(T)
+    x = normal_u8_device(torch, T, 4096, 128.0, 16.0, 3)
+    planes = plan.alloc_planes(T)
+    out = plan.alloc_search_out(1 << 20)
+    ws = plan.workspace(T)
+    side = torch.cuda.Stream()
+
+    def step():
+        plan.dedisperse_search(x, planes=planes, out=out, workspace=ws, stream=side)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    A.check(L.sdd_profile_enable(1), "profile")
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    stage = {}
+    for name, sid in A.STAGES.items():
+        if name in ("sift", "ffa"):
+            continue
+        ms, n = C.c_double(), C.c_int64()
+        A.check(L.sdd_profile_read(sid, C.byref(ms), C.byref(n)), "profile_read")
+        stage[name] = ms.value / steps            # per step, all launches of the stage
+    L.sdd_profile_enable(0)
+    ndm = plan.ndm
+    own = sum(4096 * ndm[r] * g["n_owned_r"][r] for r in range(plan.nranges))
+    native = 4096 * plan.ndm_total * g["n_owned"]
+    decs = sorted({d for d in plan.decimation if d > 1})
+    dec_bytes = 4096 * T + sum(2 * 4096 * (T // d) for d in decs)
+    ct_bytes = 2 * 4096 * T
+    dd_ms = stage["dedisperse"]
+    res = {"workload": "multi-range: 4096 ch 750-550 MHz, 81.92 us, 2^19 owned samples, DM "
+                       "0-100/0.1, 100-300/0.2 dec 2, 300-700/0.5 dec 4, 700-1500/1 dec 8, "
+                       "1500-3000/2 dec 16, widths 1..256, spectra uint8 N(128,16)",
+           "ndm": list(ndm), "n_owned_r": g["n_owned_r"], "nsamp_in": T,
+           "tiles": [list(plan.get_tile(r)) for r in range(plan.nranges)],
+           "ms_per_step": round(dt * 1e3, 3),
+           "value_range_own": round(own / dt / 1e9, 2),
+           "value_native_rate": round(native / dt / 1e9, 2), "unit": UNIT,
+           "stage_ms": {k: round(v, 4) for k, v in stage.items()},
+           "dedisperse_adds_per_s": round(own / (dd_ms / 1e3) / 1e12, 3),
+           "roofline_decimate": {"bound": "hbm", "bytes": dec_bytes,
+                                 "achieved_gbps": round(dec_bytes / stage["decimate"] / 1e6, 1),
+                                 "peak_gbps": 8000.0,
+                                 "frac": round(dec_bytes / stage["decimate"] / 1e6 / 8000.0, 4)},
+           "roofline_corner_turn": {"bound": "hbm", "bytes": ct_bytes,
+                                    "achieved_gbps": round(ct_bytes / stage["corner_turn"] / 1e6,
+                                                           1),
+                                    "peak_gbps": 8000.0,
+                                    "frac": round(ct_bytes / stage["corner_turn"] / 1e6 / 8000.0,
+                                                  4)},
+           "candidates": int(out.ncand.cpu()[0])}
+    log(f"multi-range: {res}")
+    del x, planes, out, ws
+    return res
+
+
 def batch_bench(sdd, torch, nbeams: int):
     """nbeams beams of 4096 channels with owned lengths U[2^16, 2^18], 2048
     trials 0-1000, widths 1..64: per-beam dedisperse_search calls vs one
@@ -403,13 +558,17 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--cpu-rows", type=int, default=48,
+    ap.add_argument("--cpu-rows", type=int, default=32,
                     help="DM trials of the oracle's bounded CPU sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the streaming-server run")
     ap.add_argument("--serve-beams", type=int, default=160)
     ap.add_argument("--serve-chunks", type=int, default=4, help="chunks per beam, saturated run")
-    ap.add_argument("--serve-periods", type=int, default=2, help="measured real-time periods")
+    ap.add_argument("--serve-periods", type=int, default=5,
+                    help="measured real-time periods, mixed channel counts")
+    ap.add_argument("--serve-periods-4096", type=int, default=20,
+                    help="measured real-time periods, every beam at 4096 channels")
+    ap.add_argument("--no-multi-range", action="store_true", help="skip the multi-range run")
     ap.add_argument("--serve-batch", type=int, default=16)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-beams run")
     ap.add_argument("--batch-beams", type=int, default=32)
@@ -422,6 +581,10 @@ def main() -> int:
               "whole-job throughput at N GPUs is N independent copies of this run; "
               "only the one-GPU run is measured.", file=sys.stderr)
         return 2
+
+    # the probe runs in its own process before this one touches the GPU
+    ceil = probe_ceilings()
+    log(f"ceilings: {ceil}")
 
     import torch
     import synth
@@ -504,7 +667,24 @@ def main() -> int:
                                             4)}
                              if list(plan.get_tile(0)) == LDS_BYTES_PER_ADD["tile"] else None)},
         "cpu_baseline": None,
+        "ceilings": ceil,
     }
+    rf = res["roofline"]
+    if ceil:
+        # measured LDS rate (ds_read_b128) in place of the stored one
+        lds_peak = ceil["ds_read_b128"]["bytes_per_clk_cu"] * 256 * 2.4e9 / 1e12
+        if rf["lds"]:
+            rf["lds"]["peak"] = round(lds_peak, 1)
+            rf["lds"]["frac"] = round(rf["lds"]["achieved"] / lds_peak, 4)
+            rf["lds"]["peak_source"] = "ds_read_b128 rate measured by the ceiling probe"
+        # the kernel's own instruction-mix ceiling: adds per VALU instruction
+        # (SQ counters of this tile) x the measured VOP3 issue rate
+        if list(plan.get_tile(0)) == ADDS_PER_VALU["tile"]:
+            rate = ceil["v_add3_u32"]["wave_instr_per_clk_cu"]
+            ic = ADDS_PER_VALU["adds"] * rate * 256 * 2.4e9 / 1e12
+            rf["issue"] = {"adds_per_valu_instr": ADDS_PER_VALU["adds"],
+                           "valu_instr_per_clk_cu": rate, "ceiling": round(ic, 2),
+                           "unit": "TOP/s", "frac": round(achieved / ic, 4)}
     res["sift"] = sift_bench(sdd, torch, plan, out, float(w.dm_list[1] - w.dm_list[0]), 1 << 16)
     log(f"sift: {res['sift']}")
     res["rfi"] = rfi_bench(sdd, torch, plan, xt, planes, out, ws)
@@ -532,6 +712,10 @@ def main() -> int:
     res["batched"] = None
     del xt, planes, ws, out
     torch.cuda.empty_cache()
+    res["multi_range"] = None
+    if not args.no_multi_range:
+        res["multi_range"] = multi_range_bench(sdd, torch, 3, 1)
+        torch.cuda.empty_cache()
     if not args.no_batch:
         res["batched"] = batch_bench(sdd, torch, args.batch_beams)
         torch.cuda.empty_cache()
@@ -541,7 +725,7 @@ def main() -> int:
         torch.cuda.empty_cache()
         # the same loop with every beam at the full 4096 channels
         res["serving_4096"] = serve_bench(sdd, torch, args.serve_beams, args.serve_chunks,
-                                          args.serve_periods, args.serve_batch, 2,
+                                          args.serve_periods_4096, args.serve_batch, 2,
                                           chans=(4096,))
     print(json.dumps(res), flush=True)
     return 0

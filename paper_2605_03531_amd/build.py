@@ -13,6 +13,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libspotdd.so")
+PROBE = os.path.join(PKG, "probe", "sdd_ceilings")
 OBJ = os.path.join(ROOT, "_build", "obj")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -50,8 +51,15 @@ def build(verbose: bool = True) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, OUT)
+    # the ceiling probe the benchmark reads its VALU and LDS rates from
+    probe = os.path.join(PKG, "probe", "ceilings.hip")
+    cmd = [HIPCC, *COMMON, probe, "-o", PROBE + ".tmp"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed on {probe}:\n{r.stdout}\n{r.stderr}")
+    os.replace(PROBE + ".tmp", PROBE)
     if verbose:
-        print(f"built {OUT} from {len(srcs)} sources", flush=True)
+        print(f"built {OUT} from {len(srcs)} sources, and {PROBE}", flush=True)
     return OUT
 
 

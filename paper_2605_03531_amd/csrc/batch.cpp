@@ -1,7 +1,7 @@
 // Batched dedispersion + search of many chunks (beams) in one call: the
 // chunks' corner turns and decimations, then one persistent dedispersion
 // launch over the tiles of every (beam, DM range) job that shares an LDS tile
-// shape, then each chunk's search. Optionally the whole sequence is captured
+// shape and input element type, then each chunk's search. Optionally the whole sequence is captured
 // once as a HIP graph and replayed while the batch's buffers stay the same.
 #include <algorithm>
 #include <cstring>
@@ -29,7 +29,9 @@ sdd_status launch_jobs_persistent(const std::vector<DedispArgs>& jobs, hipStream
     int n = 0;
     int32_t tiles = 0, max_win = 0;
     for (size_t k = i; k < jobs.size() && n < kMaxJobs; ++k) {
-      if (done[k] || shape[k] != shape[i]) continue;
+      // one launch takes jobs of one shape and one element type (uint8 rows,
+      // or the uint16 rows of decimated ranges)
+      if (done[k] || shape[k] != shape[i] || la[k].es != la[i].es) continue;
       m.jobs[n] = la[k];
       m.tile_base[n] = tiles;
       tiles += la[k].n_dtiles * la[k].n_ttiles;

@@ -54,10 +54,25 @@ sdd_status prep_item(const sdd_plan* p, const CallGeom& cg, const uint8_t* d_in,
     src = pre->rows;
     src_pitch = pre->rows_pitch;
   }
-  // each decimation is built from the largest smaller one that divides it
   std::vector<uint16_t*> dbuf(L.decs.size());
-  for (size_t k = 0; k < L.decs.size(); ++k) {
+  for (size_t k = 0; k < L.decs.size(); ++k)
     dbuf[k] = reinterpret_cast<uint16_t*>(ws + L.dec_off[k]);
+  // decimations 2, 4, 8, 16 only: one pass over the uint8 rows
+  bool pow2 = !L.decs.empty();
+  for (int32_t d : L.decs) pow2 = pow2 && (d == 2 || d == 4 || d == 8 || d == 16);
+  if (pow2) {
+    DecLevels lv;
+    for (size_t k = 0; k < L.decs.size(); ++k) {
+      const int l = L.decs[k] == 2 ? 0 : L.decs[k] == 4 ? 1 : L.decs[k] == 8 ? 2 : 3;
+      lv.out[l] = dbuf[k];
+      lv.pitch[l] = L.dec_pitch[k];
+      lv.len[l] = L.dec_len[k];
+    }
+    StageTimer tm(SDD_STAGE_DECIMATE, s);
+    SDD_HIP_TRY(launch_decimate_pow2(src, src_pitch, nsamp_in, p->nchan, lv, s));
+  }
+  // otherwise each decimation is built from the largest smaller one that divides it
+  for (size_t k = 0; k < L.decs.size() && !pow2; ++k) {
     int32_t d = L.decs[k];
     int from = -1;
     for (int j = (int)k - 1; j >= 0; --j)
@@ -285,3 +300,4 @@ extern "C" sdd_status sdd_dedisperse_search(const sdd_plan* p, const uint8_t* d_
   return run_search(p, cg, (const uint32_t* const*)d_planes, plane_pitch, d_best, d_stats,
                     d_cands, cap, d_ncand, (uint8_t*)d_ws, s);
 }
+

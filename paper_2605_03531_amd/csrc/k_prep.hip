@@ -118,7 +118,82 @@ __global__ __launch_bounds__(256) void k_decimate(const Tin* __restrict__ in, in
   }
 }
 
+// Every power-of-two decimation up to 16 of uint8 rows in one pass. A thread
+// owns 16 consecutive samples (one 16-byte load), forms the exact pairwise
+// sums level by level (2, 4, 8, 16 samples) and writes the levels the plan
+// uses; a wavefront's writes of one level are contiguous. Each input byte is
+// read once; each level's rows are written once (1 + 2 * sum 1/dec bytes of
+// traffic per input byte, against the pass-per-level form that re-reads every
+// level it builds from).
+__global__ __launch_bounds__(256) void k_decimate_pow2(const uint8_t* __restrict__ in,
+                                                       int64_t in_pitch, int64_t nsamp,
+                                                       int32_t nchan, int vec, DecLevels lv) {
+  const int64_t t = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 16;
+  if (t >= nsamp) return;
+  for (int32_t c = blockIdx.y; c < nchan; c += gridDim.y) {
+    const uint8_t* src = in + (int64_t)c * in_pitch + t;
+    uint32_t w[4];
+    if (vec && t + 16 <= nsamp) {
+      const uint4 v = *reinterpret_cast<const uint4*>(src);
+      w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
+    } else {
+      // samples past the row end read as 0; no output that uses them is written
+      for (int q = 0; q < 4; ++q) w[q] = 0u;
+      for (int b = 0; b < 16 && t + b < nsamp; ++b) w[b >> 2] |= (uint32_t)src[b] << (8 * (b & 3));
+    }
+    // level 1: sums of 2 samples, as packed 16-bit pairs (s1[q] = outputs 2q, 2q+1)
+    uint32_t s1[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      s1[q] = ((w[q] & 0xffu) + ((w[q] >> 8) & 0xffu)) |
+              ((((w[q] >> 16) & 0xffu) + (w[q] >> 24)) << 16);
+    uint32_t s2[2], s3, s4;
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+      s2[q] = ((s1[2 * q] & 0xffffu) + (s1[2 * q] >> 16)) |
+              (((s1[2 * q + 1] & 0xffffu) + (s1[2 * q + 1] >> 16)) << 16);
+    s3 = ((s2[0] & 0xffffu) + (s2[0] >> 16)) | (((s2[1] & 0xffffu) + (s2[1] >> 16)) << 16);
+    s4 = (s3 & 0xffffu) + (s3 >> 16);
+    // level l holds 16 >> l outputs starting at output t >> l
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      uint16_t* o = lv.out[l];
+      if (!o) continue;
+      const int n = 8 >> l;                   // outputs of this thread at level l
+      const int64_t j0 = t >> (l + 1);
+      uint16_t* dst = o + (int64_t)c * lv.pitch[l] + j0;
+      const uint32_t* vals = l == 0 ? s1 : l == 1 ? s2 : l == 2 ? &s3 : &s4;
+      if (lv.vec[l] && j0 + n <= lv.len[l]) {
+        if (l == 0)
+          *reinterpret_cast<uint4*>(dst) = make_uint4(s1[0], s1[1], s1[2], s1[3]);
+        else if (l == 1)
+          *reinterpret_cast<uint2*>(dst) = make_uint2(s2[0], s2[1]);
+        else if (l == 2)
+          *reinterpret_cast<uint32_t*>(dst) = s3;
+        else
+          *dst = (uint16_t)s4;
+      } else {
+        for (int k = 0; k < n && j0 + k < lv.len[l]; ++k)
+          dst[k] = (uint16_t)(vals[k >> 1] >> (16 * (k & 1)));
+      }
+    }
+  }
+}
+
 }  // namespace
+
+hipError_t launch_decimate_pow2(const uint8_t* in, int64_t in_pitch, int64_t nsamp, int32_t nchan,
+                                const DecLevels& lv, hipStream_t s) {
+  DecLevels l = lv;
+  for (int k = 0; k < 4; ++k) {
+    const int bytes = 16 >> k;  // bytes of one thread's outputs at level k
+    l.vec[k] = l.out[k] && ((uintptr_t)l.out[k] % bytes == 0) && ((l.pitch[k] * 2) % bytes == 0);
+  }
+  const int vec = ((uintptr_t)in % 16 == 0) && (in_pitch % 16 == 0);
+  dim3 grid((unsigned)((nsamp + 4095) / 4096), (unsigned)(nchan < 1024 ? nchan : 1024));
+  hipLaunchKernelGGL(k_decimate_pow2, grid, dim3(256), 0, s, in, in_pitch, nsamp, nchan, vec, l);
+  return hipGetLastError();
+}
 
 hipError_t launch_corner_turn(const uint8_t* in, int64_t nsamp, int64_t in_pitch, int32_t nchan,
                               uint8_t* out, int64_t out_pitch, hipStream_t s, int64_t ring_rows,

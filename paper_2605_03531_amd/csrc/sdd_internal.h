@@ -172,6 +172,16 @@ hipError_t launch_precond_rows(const uint8_t* in, int64_t in_pitch, int64_t nsam
                                const uint8_t* lut, const uint8_t* tmask, uint8_t* out,
                                int64_t out_pitch, hipStream_t s);
 // out[c][j] = sum_{k<factor} in[c][j*factor+k], j < out_len; in is u8 or u16.
+// Power-of-two decimation levels 2, 4, 8, 16 (index 0..3) built in one pass
+// from uint8 rows; out[l] == nullptr skips level l.
+struct DecLevels {
+  uint16_t* out[4] = {nullptr, nullptr, nullptr, nullptr};
+  int64_t pitch[4] = {0, 0, 0, 0};  // elements
+  int64_t len[4] = {0, 0, 0, 0};    // outputs per row
+  int vec[4] = {0, 0, 0, 0};        // set by the launcher: aligned vector stores
+};
+hipError_t launch_decimate_pow2(const uint8_t* in, int64_t in_pitch, int64_t nsamp, int32_t nchan,
+                                const DecLevels& lv, hipStream_t s);
 hipError_t launch_decimate(const void* in, int in_bytes, int64_t in_pitch, int32_t nchan,
                            int32_t factor, uint16_t* out, int64_t out_pitch, int64_t out_len,
                            hipStream_t s);

@@ -434,3 +434,43 @@ def test_saturated_input_every_tile_grid_and_persistent():
                 else:
                     compare_rows(spec, ph, expect[name])
     assert ran >= 3
+
+
+@pytest.mark.parametrize("case", ["pow2_levels_skipped", "pow2_unaligned_rows", "not_pow2"])
+def test_decimation_paths_exact(case):
+    """Decimated ranges through both decimation paths: the one-pass kernel
+    for decimations among 2, 4, 8, 16 (with levels the plan does not use
+    skipped, and channel rows whose pitch is not a multiple of 16 bytes, so
+    its loads fall back to bytes), and the level-by-level kernel for other
+    factors (3 and 6, 6 built from 3). A ragged owned length leaves a partial
+    group of samples at the row end. Full planes against the oracle."""
+    import torch
+    import paper_2605_03531_amd as sdd
+    f = np.linspace(500.0, 300.0, 72)
+    if case == "not_pow2":
+        ranges = [(0.0, 10.0, 1.0, 1), (10.0, 30.0, 2.0, 3), (30.0, 60.0, 3.0, 6)]
+    else:
+        ranges = [(0.0, 10.0, 1.0, 1), (10.0, 30.0, 2.0, 2), (30.0, 90.0, 4.0, 16)]
+    kw = dict(freqs_mhz=f, t_samp=1e-3, ranges=ranges, widths=[1, 3, 8], cand_block=300,
+              threshold=4.0)
+    spec = oracle_plan(kw)
+    T = spec.overlap + 4000 + 48 + 5
+    x = synth.filterbank(77, 72, T, 110.0, 20.0)
+    synth.inject_pulse(x, oracle.delay_table(f, [40.0], 1e-3)[0], 1500, 12, 20.0)
+    orc = oracle.run(spec, x)
+    if case == "pow2_unaligned_rows":
+        plan = _make(kw, "chan")
+        buf = np.zeros((72, T + 3), dtype=np.uint8)
+        buf[:, :T] = x
+        xt = torch.from_numpy(buf).to("cuda:0")[:, :T]
+        planes = plan.alloc_planes(T)
+        _, out = plan.dedisperse_search(xt, planes=planes)
+        torch.cuda.synchronize()
+        g = plan.geometry(T)
+        ph = [sdd.plane_host(planes[r], g["plane_cols"][r]) for r in range(3)]
+        res = out.host()
+    else:
+        plan = _make(kw, "time")
+        ph, res, g = gpu_run(plan, x, time_major=True)
+    compare_rows(spec, ph, orc)
+    compare_search(spec, res, orc, full_rows=True)
