@@ -288,6 +288,27 @@ sdd_status sdd_dedisperse_search(const sdd_plan* plan, const uint8_t* d_in, int6
                                  int32_t* d_ncand, void* d_workspace, int64_t ws_bytes,
                                  void* stream);
 
+/* sdd_dedisperse_search for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same path and results, with every scratch buffer (corner-
+ * turned rows, decimated rows, search partials; the planes too when d_planes
+ * is NULL) in a static device array of the library, 256 MiB, one copy per
+ * device, held until the process ends. It calls no hipMalloc, hipFree or
+ * other allocating routine. ENOMEM if the chunk needs more than 256 MiB of
+ * scratch (geometry.workspace_bytes, or workspace_bytes_planes with NULL
+ * planes); ESTATE if the plan's device tables do not exist yet (any other
+ * compute call with the plan creates them); other errors as
+ * sdd_dedisperse_search. Every call on one device shares that device's
+ * array, which keeps the last call's contents: calls that overlap on one
+ * device (other host threads, or other streams before the first call's work
+ * is done) race and corrupt each other's results. */
+sdd_status sdd_dedisperse_search_static(const sdd_plan* plan, const uint8_t* d_in,
+                                        int64_t nsamp_in, int64_t in_pitch,
+                                        uint32_t* const* d_planes, const int64_t* plane_pitch,
+                                        sdd_dm_best* d_best, sdd_dm_stats* d_stats,
+                                        sdd_candidate* d_cands, int32_t cap, int32_t* d_ncand,
+                                        void* stream);
+
 /* ---- batches of chunks (many beams, uneven lengths) ---------------------- */
 
 /* One chunk of one beam in a batch; fields as in sdd_dedisperse_search.

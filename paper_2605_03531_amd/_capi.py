@@ -134,6 +134,8 @@ _PROTOS = {
                                 vp, i64, vp]),
     "sdd_dedisperse_search": (i32, [vp, vp, i64, i64, C.POINTER(vp), C.POINTER(i64), vp, vp,
                                     vp, i32, vp, vp, i64, vp]),
+    "sdd_dedisperse_search_static": (i32, [vp, vp, i64, i64, C.POINTER(vp), C.POINTER(i64),
+                                           vp, vp, vp, i32, vp, vp]),
     "sdd_batch_workspace_size": (i32, [C.POINTER(BatchItem), i32, C.POINTER(i64)]),
     "sdd_batch_dedisperse_search": (i32, [C.POINTER(BatchItem), i32, i32, vp, i64, vp]),
     "sdd_batch_graph_clear": (i32, []),

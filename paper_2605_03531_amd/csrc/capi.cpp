@@ -3,6 +3,7 @@
 // dedispersion per range -> boxcar search).
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 
 #include "sdd_internal.h"
 
@@ -301,3 +302,91 @@ extern "C" sdd_status sdd_dedisperse_search(const sdd_plan* p, const uint8_t* d_
                     d_cands, cap, d_ncand, (uint8_t*)d_ws, s);
 }
 
+// ---- allocation-free variant ------------------------------------------------
+//
+// The scratch of sdd_dedisperse_search_static: a device array in this module,
+// one copy on each device the library runs on, held until the process ends.
+// Host code never passes `scratch` itself (its host-side name is not a device
+// address); it passes the address hipGetSymbolAddress returns for the device,
+// looked up once per device on the entry point's first call there.
+
+namespace {
+
+constexpr int64_t kStaticScratchBytes = (int64_t)256 << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) uint8_t scratch[kStaticScratchBytes];
+
+std::mutex g_scratch_mu;
+uint8_t* g_scratch[kMaxDevices] = {nullptr};
+
+// Device address of this device's copy of `scratch` (caller has the device
+// current).
+sdd_status static_scratch(int device, uint8_t** out) {
+  if (device < 0 || device >= kMaxDevices) SDD_FAIL(SDD_EINVAL, "device %d out of range", device);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      SDD_FAIL(SDD_EDEVICE, "static scratch address on device %d: %s", device,
+               hipGetErrorString(e));
+    g_scratch[device] = static_cast<uint8_t*>(ptr);
+  }
+  *out = g_scratch[device];
+  return SDD_OK;
+}
+
+}  // namespace
+
+extern "C" sdd_status sdd_dedisperse_search_static(const sdd_plan* p, const uint8_t* d_in,
+                                                   int64_t nsamp_in, int64_t in_pitch,
+                                                   uint32_t* const* d_planes,
+                                                   const int64_t* plane_pitch,
+                                                   sdd_dm_best* d_best, sdd_dm_stats* d_stats,
+                                                   sdd_candidate* d_cands, int32_t cap,
+                                                   int32_t* d_ncand, void* stream) {
+  clear_error();
+  if (!p) SDD_FAIL(SDD_EINVAL, "null plan");
+  if (p->widths.empty()) SDD_FAIL(SDD_EINVAL, "plan has no boxcar widths");
+  if (!d_best || !d_ncand || cap < 0 || (cap > 0 && !d_cands))
+    SDD_FAIL(SDD_EINVAL, "null best/ncand, or null candidates with cap > 0");
+  CallGeom cg;
+  sdd_status st = plan_geometry(p, nsamp_in, &cg);
+  if (st != SDD_OK) return st;
+  if ((st = check_input(p, d_in, nsamp_in, in_pitch)) != SDD_OK) return st;
+  const bool lib_planes = (d_planes == nullptr);
+  const int64_t need = lib_planes ? cg.ws.total_planes : cg.ws.total;
+  if (need > kStaticScratchBytes)
+    SDD_FAIL(SDD_ENOMEM, "this chunk needs %lld bytes of scratch; the static scratch holds %lld",
+             (long long)need, (long long)kStaticScratchBytes);
+  if (!lib_planes &&
+      (st = check_planes(p, cg, (const void* const*)d_planes, plane_pitch)) != SDD_OK)
+    return st;
+  {
+    // the plan's device tables are allocated by the first regular compute
+    // call; this entry point allocates nothing, so it needs them in place
+    std::lock_guard<std::mutex> lk(p->mu);
+    if (p->uploaded_device != p->device)
+      SDD_FAIL(SDD_ESTATE, "the plan's device tables do not exist yet: run any other compute "
+                           "call with this plan first");
+  }
+  DeviceGuard dg(p->device);
+  if (!dg.ok) SDD_FAIL(SDD_EDEVICE, "cannot select device %d", p->device);
+  uint8_t* ws = nullptr;
+  if ((st = static_scratch(p->device, &ws)) != SDD_OK) return st;
+  uint32_t* own[SDD_MAX_RANGES];
+  int64_t own_pitch[SDD_MAX_RANGES];
+  if (lib_planes) {
+    for (size_t r = 0; r < p->ranges.size(); ++r) {
+      own[r] = reinterpret_cast<uint32_t*>(ws + cg.ws.plane_off[r]);
+      own_pitch[r] = cg.ws.plane_pitch[r];
+    }
+    d_planes = own;
+    plane_pitch = own_pitch;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  st = run_dedisperse(p, cg, d_in, nsamp_in, in_pitch, d_planes, plane_pitch, ws, s);
+  if (st != SDD_OK) return st;
+  return run_search(p, cg, (const uint32_t* const*)d_planes, plane_pitch, d_best, d_stats,
+                    d_cands, cap, d_ncand, ws, s);
+}

@@ -302,6 +302,19 @@ class Plan:
                                                   *common), "sdd_dedisperse_search")
         return planes, out
 
+
+    def dedisperse_search_static(self, x, planes, out: SearchOut, stream=None):
+        """sdd_dedisperse_search_static: the path with the library's static
+        device scratch (no allocation in the call). planes may be None (kept
+        in the scratch, not returned); out must be allocated beforehand."""
+        nsamp, pitch = self._input(x)
+        ptrs, pp = (None, None) if planes is None else self._planes(planes)
+        cap = out.cands.numel() // CAND_DTYPE.itemsize
+        A.check(A.lib().sdd_dedisperse_search_static(
+            self._p, x.data_ptr(), nsamp, pitch, ptrs, pp, out.best.data_ptr(),
+            out.stats.data_ptr(), out.cands.data_ptr(), cap, out.ncand.data_ptr(),
+            _stream_handle(stream, self.device)), "sdd_dedisperse_search_static")
+        return planes, out
     def rfi_estimate(self, x, median_window: int = 21, rounds: int = 2,
                      chan_sigma: float = 4.0, time_sigma: float = 3.0, stream=None):
         """Bandpass and flags of one chunk in this plan's layout
