@@ -571,6 +571,9 @@ def main() -> int:
     ap.add_argument("--no-multi-range", action="store_true", help="skip the multi-range run")
     ap.add_argument("--serve-batch", type=int, default=16)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-beams run")
+    ap.add_argument("--only-batch", action="store_true",
+                    help="run only the batched-beams comparison (for profiling its launches); "
+                         "prints its JSON object")
     ap.add_argument("--batch-beams", type=int, default=32)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, copy 1 GiB device-to-device three times "
@@ -582,6 +585,11 @@ def main() -> int:
               "only the one-GPU run is measured.", file=sys.stderr)
         return 2
 
+    if args.only_batch:
+        import torch
+        import paper_2605_03531_amd as sdd
+        print(json.dumps({"batched": batch_bench(sdd, torch, args.batch_beams)}), flush=True)
+        return 0
     # the probe runs in its own process before this one touches the GPU
     ceil = probe_ceilings()
     log(f"ceilings: {ceil}")

@@ -13,7 +13,20 @@
 
 namespace sdd {
 
-sdd_status launch_jobs_persistent(const std::vector<DedispArgs>& jobs, hipStream_t s) {
+namespace {
+__global__ void k_zero_tickets(uint32_t* p, int32_t n) {
+  if ((int32_t)threadIdx.x < n) p[threadIdx.x] = 0u;
+}
+}  // namespace
+
+sdd_status launch_jobs_persistent(const std::vector<DedispArgs>& jobs, uint32_t* tickets,
+                                  hipStream_t s) {
+  // 8 tile counters per launch, zeroed by a kernel (no memset node in a
+  // captured graph); one launch per group of jobs of one shape and element type
+  hipLaunchKernelGGL(k_zero_tickets, dim3(1), dim3(kBatchTickets), 0, s, tickets,
+                     (int32_t)kBatchTickets);
+  SDD_HIP_TRY(hipGetLastError());
+  int32_t launch = 0;
   std::vector<LdsArgs> la(jobs.size());
   std::vector<int> shape(jobs.size());
   for (size_t i = 0; i < jobs.size(); ++i) shape[i] = lds_args_for(jobs[i], &la[i]);
@@ -41,6 +54,11 @@ sdd_status launch_jobs_persistent(const std::vector<DedispArgs>& jobs, hipStream
     }
     m.tile_base[n] = tiles;
     m.njobs = n;
+    if (8 * (launch + 1) > kBatchTickets) {
+      set_error("internal: more than %d persistent launches in one batch", kBatchTickets / 8);
+      return SDD_EINVAL;
+    }
+    m.tickets = tickets + 8 * launch++;
     SDD_HIP_TRY(launch_dedisperse_lds_multi(m, max_win, shape[i], s));
   }
   return SDD_OK;
@@ -67,8 +85,14 @@ sdd_status batch_layout(const BatchJob* items, int32_t n, std::vector<ItemGeom>*
     g.ws_bytes = it.d_planes ? g.cg.ws.total : g.cg.ws.total_planes;
     off = align256(off + g.ws_bytes);
   }
-  *total = off;
+  // the persistent launch's tile counters after the items
+  *total = off + align256(4 * kBatchTickets);
   return SDD_OK;
+}
+
+int64_t batch_tickets_off(const std::vector<ItemGeom>& geo) {
+  const ItemGeom& g = geo.back();
+  return align256(g.ws_off + g.ws_bytes);
 }
 
 namespace {
@@ -144,7 +168,8 @@ sdd_status enqueue_batch(const BatchJob* items, int32_t n, int32_t flags,
   }
   if (!(flags & SDD_BATCH_PER_ITEM)) {
     StageTimer tm(SDD_STAGE_DEDISPERSE, s);
-    sdd_status st = launch_jobs_persistent(jobs, s);
+    sdd_status st = launch_jobs_persistent(
+        jobs, reinterpret_cast<uint32_t*>(ws + batch_tickets_off(geo)), s);
     if (st != SDD_OK) return st;
   }
   for (int32_t k = 0; k < n; ++k) {

@@ -53,6 +53,7 @@ struct MultiArgs {
   LdsArgs jobs[kMaxJobs];
   int32_t tile_base[kMaxJobs + 1];  // first global tile of each job; [njobs] = total
   int32_t njobs;
+  uint32_t* tickets;                // 8 zeroed counters, one per XCD
 };
 
 hipError_t launch_dedisperse_lds(const LdsArgs& a, int shape, hipStream_t s);

@@ -402,21 +402,29 @@ __global__ __launch_bounds__(64 * WD * WT) void k_dedisp_lds(LdsArgs a) {
 
 // Persistent form for a batch of jobs (beams x DM ranges with the same tile
 // shape): the global tile list (job by job, time-tile-major inside a job) is
-// cut into 8 contiguous parts, one per XCD. The workgroups of an XCD walk its
-// part in rounds: in round r workgroup k of the XCD takes tile r * n + k, so
-// the tiles running together on an XCD stay neighbours (and share input in
-// its L2) as they do in the grid form, without a tail per job.
+// cut into 8 contiguous parts, one per XCD. The workgroups of an XCD take the
+// tiles of its part in order from a counter of that XCD, each workgroup its
+// next tile when it finishes one (as the hardware hands out the workgroups of
+// a grid), so the tiles running together on an XCD are the latest few dozen
+// of its part: neighbours that share input in its L2. (A fixed assignment,
+// tile r * n + k to workgroup k in round r, lets the workgroups drift apart
+// by many rounds over a long batch and loses that sharing.)
 template <int D, int M, int WD, int WT, int CS, int NLD, int F, int ES>
 __global__ __launch_bounds__(64 * WD * WT) void k_dedisp_lds_multi(MultiArgs m) {
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+  __shared__ int32_t ticket;
   const int32_t total = m.tile_base[m.njobs];
   const int xcd = blockIdx.x & 7;                  // workgroups go to XCDs round-robin
-  const int32_t k = blockIdx.x >> 3;               // index among this XCD's workgroups
-  const int32_t n = (int32_t)(gridDim.x >> 3);     // workgroups per XCD (grid is a multiple of 8)
   const int32_t lo = (int32_t)(((int64_t)total * xcd) >> 3);
   const int32_t hi = (int32_t)(((int64_t)total * (xcd + 1)) >> 3);
   int j = 0;
-  for (int32_t t = lo + k; t < hi; t += n) {
+  for (;;) {
+    // every thread reads the ticket before the tile's first barrier, so the
+    // next write (after the tile's last barrier) cannot overtake a read
+    if (threadIdx.x == 0) ticket = (int32_t)atomicAdd(m.tickets + xcd, 1u);
+    __syncthreads();
+    const int32_t t = lo + ticket;
+    if (t >= hi) break;  // the counter only grows: every workgroup gets here
     while (j + 1 < m.njobs && t >= m.tile_base[j + 1]) ++j;
     const LdsArgs& a = m.jobs[j];
     const int32_t L = t - m.tile_base[j];

@@ -275,7 +275,11 @@ sdd_status check_planes(const sdd_plan* p, const CallGeom& cg, const void* const
                         const int64_t* pitch);
 // Dedispersion of a set of jobs: jobs sharing an LDS tile shape go through the
 // persistent multi-job kernel; the rest are launched one by one.
-sdd_status launch_jobs_persistent(const std::vector<DedispArgs>& jobs, hipStream_t s);
+// Tile counters a batch workspace holds for its persistent launches (8 per
+// launch: one per XCD).
+constexpr int32_t kBatchTickets = 64;
+sdd_status launch_jobs_persistent(const std::vector<DedispArgs>& jobs, uint32_t* tickets,
+                                  hipStream_t s);
 
 // ---- batches (batch.cpp) ------------------------------------------------
 
@@ -294,6 +298,7 @@ struct ItemGeom {
 };
 sdd_status batch_layout(const BatchJob* items, int32_t n, std::vector<ItemGeom>* out,
                         int64_t* total);
+int64_t batch_tickets_off(const std::vector<ItemGeom>& geo);
 sdd_status enqueue_batch(const BatchJob* items, int32_t n, int32_t flags,
                          std::vector<ItemGeom>& geo, uint8_t* ws, hipStream_t s);
 

@@ -161,7 +161,8 @@ int64_t item_workspace(const sdd_plan* p, int64_t N) {
 
 // Bytes a slot needs for max_batch chunks of item_ws each.
 int64_t slot_ws_bytes(const sdd_server* s, int64_t item_ws) {
-  return (int64_t)s->d.max_batch * align256(item_ws);
+  // items, then the persistent launch's tile counters
+  return (int64_t)s->d.max_batch * align256(item_ws) + align256(4 * kBatchTickets);
 }
 
 bool chunk_ready(const sdd_stream* st, int64_t k) {
