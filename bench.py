@@ -574,6 +574,9 @@ def main() -> int:
     ap.add_argument("--only-batch", action="store_true",
                     help="run only the batched-beams comparison (for profiling its launches); "
                          "prints its JSON object")
+    ap.add_argument("--only-multi-range", action="store_true",
+                    help="run only the multi-range workload (for profiling its kernels); prints "
+                         "its JSON object")
     ap.add_argument("--batch-beams", type=int, default=32)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, copy 1 GiB device-to-device three times "
@@ -585,10 +588,14 @@ def main() -> int:
               "only the one-GPU run is measured.", file=sys.stderr)
         return 2
 
-    if args.only_batch:
+    if args.only_batch or args.only_multi_range:
         import torch
         import paper_2605_03531_amd as sdd
-        print(json.dumps({"batched": batch_bench(sdd, torch, args.batch_beams)}), flush=True)
+        if args.only_batch:
+            print(json.dumps({"batched": batch_bench(sdd, torch, args.batch_beams)}), flush=True)
+        else:
+            print(json.dumps({"multi_range": multi_range_bench(sdd, torch, args.steps,
+                                                               args.warmup)}), flush=True)
         return 0
     # the probe runs in its own process before this one touches the GPU
     ceil = probe_ceilings()

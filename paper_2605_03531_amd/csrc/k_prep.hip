@@ -81,6 +81,78 @@ __global__ __launch_bounds__(256) void k_corner_turn(const uint8_t* __restrict__
   }
 }
 
+// Corner turn of 16-byte-aligned spectra (in_pitch and the base a multiple of
+// 16, nchan a multiple of 128, no pre-conditioning maps): a workgroup turns
+// 128 channels x 128 samples. Thread (g, q), g < 8, q < 32, loads 16
+// channels (one 16-byte load) of each of the 4 spectra 4q..4q+3 (a wavefront
+// reads 128 contiguous bytes of 8 spectra per load), turns each 4 x 4 byte
+// block in registers (two rounds of v_perm) into words of 4 consecutive
+// samples of one channel and stores them to LDS; then each thread writes 16
+// samples of one channel (a wavefront writes 128 contiguous bytes of 8
+// channel rows per store). LDS rows are 136 bytes, so the word stores of a
+// wavefront (8 groups x 8 quads) hit 64 different banks.
+constexpr int kCtC = 128, kCtT = 128, kCtRow = kCtT + 8;
+__global__ __launch_bounds__(256) void k_corner_turn128(const uint8_t* __restrict__ in,
+                                                        int64_t nsamp, int64_t in_pitch,
+                                                        uint8_t* __restrict__ out,
+                                                        int64_t out_pitch, int64_t ring_rows,
+                                                        int64_t ring_start) {
+  __shared__ __attribute__((aligned(16))) uint8_t tile[kCtC * kCtRow];
+  const int tid = threadIdx.x;
+  const int g = tid & 7;          // 16-channel group
+  const int q = tid >> 3;         // 4-sample quad, 0..31
+  const int32_t c0 = blockIdx.y * kCtC;
+  const int64_t t0 = (int64_t)blockIdx.x * kCtT;
+  uint32_t w[4][4];               // [spectrum][word of 4 channels]
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int64_t t = t0 + 4 * q + r;
+    if (t < nsamp) {
+      int64_t row = t;
+      if (ring_rows > 0) {
+        row = ring_start + t;
+        row -= (row / ring_rows) * ring_rows;
+      }
+      const uint4 v = *reinterpret_cast<const uint4*>(in + row * in_pitch + c0 + 16 * g);
+      w[r][0] = v.x; w[r][1] = v.y; w[r][2] = v.z; w[r][3] = v.w;
+    } else {
+      w[r][0] = w[r][1] = w[r][2] = w[r][3] = 0u;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    // spectra 0..3 x channels 16g + 4k .. +3 -> one word of 4 samples per channel
+    const uint32_t lo01 = __builtin_amdgcn_perm(w[1][k], w[0][k], 0x05010400u);
+    const uint32_t hi01 = __builtin_amdgcn_perm(w[1][k], w[0][k], 0x07030602u);
+    const uint32_t lo23 = __builtin_amdgcn_perm(w[3][k], w[2][k], 0x05010400u);
+    const uint32_t hi23 = __builtin_amdgcn_perm(w[3][k], w[2][k], 0x07030602u);
+    const uint32_t ch[4] = {__builtin_amdgcn_perm(lo23, lo01, 0x05040100u),
+                            __builtin_amdgcn_perm(lo23, lo01, 0x07060302u),
+                            __builtin_amdgcn_perm(hi23, hi01, 0x05040100u),
+                            __builtin_amdgcn_perm(hi23, hi01, 0x07060302u)};
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      *reinterpret_cast<uint32_t*>(tile + (16 * g + 4 * k + b) * kCtRow + 4 * q) = ch[b];
+  }
+  __syncthreads();
+  // 128 channels x 8 pieces of 16 samples: thread takes pieces tid + 256 p
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    const int e = tid + 256 * p;
+    const int c = e >> 3, sp = e & 7;
+    const int64_t t = t0 + 16 * sp;
+    const uint2* src = reinterpret_cast<const uint2*>(tile + c * kCtRow + 16 * sp);
+    const uint2 a = src[0], b = src[1];
+    uint8_t* dst = out + (int64_t)(c0 + c) * out_pitch + t;
+    if (t + 16 <= nsamp) {
+      *reinterpret_cast<uint4*>(dst) = make_uint4(a.x, a.y, b.x, b.y);
+    } else {
+      const uint32_t v[4] = {a.x, a.y, b.x, b.y};
+      for (int k2 = 0; k2 < 16 && t + k2 < nsamp; ++k2) dst[k2] = (uint8_t)(v[k2 >> 2] >> (8 * (k2 & 3)));
+    }
+  }
+}
+
 // Channel rows through the pre-conditioning maps: 4 samples per thread.
 __global__ __launch_bounds__(256) void k_precond_rows(const uint8_t* __restrict__ in,
                                                       int64_t in_pitch, int64_t nsamp,
@@ -198,6 +270,13 @@ hipError_t launch_decimate_pow2(const uint8_t* in, int64_t in_pitch, int64_t nsa
 hipError_t launch_corner_turn(const uint8_t* in, int64_t nsamp, int64_t in_pitch, int32_t nchan,
                               uint8_t* out, int64_t out_pitch, hipStream_t s, int64_t ring_rows,
                               int64_t ring_start, const uint8_t* lut, const uint8_t* tmask) {
+  if (!lut && !tmask && nchan % kCtC == 0 && (uintptr_t)in % 16 == 0 && in_pitch % 16 == 0 &&
+      (uintptr_t)out % 16 == 0 && out_pitch % 16 == 0) {
+    dim3 grid((unsigned)((nsamp + kCtT - 1) / kCtT), (unsigned)(nchan / kCtC));
+    hipLaunchKernelGGL(k_corner_turn128, grid, dim3(256), 0, s, in, nsamp, in_pitch, out,
+                       out_pitch, ring_rows, ring_start);
+    return hipGetLastError();
+  }
   const int dword_in = ((uintptr_t)in % 4 == 0) && (in_pitch % 4 == 0);
   const int dword_out = ((uintptr_t)out % 4 == 0) && (out_pitch % 4 == 0);
   dim3 grid((unsigned)((nsamp + kCtTime - 1) / kCtTime), (unsigned)((nchan + kCtChan - 1) / kCtChan));

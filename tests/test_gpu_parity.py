@@ -474,3 +474,33 @@ def test_decimation_paths_exact(case):
         ph, res, g = gpu_run(plan, x, time_major=True)
     compare_rows(spec, ph, orc)
     compare_search(spec, res, orc, full_rows=True)
+
+
+@pytest.mark.parametrize("pitch", [256, 272, 264])
+def test_corner_turn_channel_tiles_ragged(pitch):
+    """Spectra-ordered input of 256 channels through both corner turns: row
+    pitches of 256 and 272 bytes take the 128-channel x 128-sample tiles
+    (16-byte loads, register transposes), 264 bytes the byte-granular
+    kernel. The number of spectra is not a multiple of 16, so the last tile
+    of every channel row ends part-way. Full planes against the oracle."""
+    import torch
+    sdd = _sdd()
+    f = np.linspace(500.0, 300.0, 256)
+    kw = dict(freqs_mhz=f, t_samp=1e-3, dm_list=np.linspace(0.0, 30.0, 24), widths=[1, 4],
+              cand_block=256, threshold=5.0)
+    spec = oracle_plan(kw)
+    T = spec.overlap + 2000 + 13
+    say(f"corner turn, 256 channels, {T} spectra, pitch {pitch}")
+    x = synth.filterbank(91, 256, T, 100.0, 25.0)
+    buf = np.zeros((T, pitch), dtype=np.uint8)
+    buf[:, :256] = x.T
+    xt = torch.from_numpy(buf).to("cuda:0")[:, :256]
+    plan = _make(kw, "time")
+    planes = plan.alloc_planes(T)
+    _, out = plan.dedisperse_search(xt, planes=planes)
+    torch.cuda.synchronize()
+    g = plan.geometry(T)
+    ph = [sdd.plane_host(planes[0], g["plane_cols"][0])]
+    orc = oracle.run(spec, x)
+    compare_rows(spec, ph, orc)
+    compare_search(spec, out.host(), orc, full_rows=True)
