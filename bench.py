@@ -31,25 +31,33 @@ sys.path.insert(0, ROOT)
 METRIC = "dedispersion Gchan·DM·samples/s; real-time beams served + p99 chunk latency"
 UNIT = "Gchan·DM·samples/s"
 WIDTHS = [1, 2, 4, 8, 16, 32, 64]
-# MI355X: 256 CUs x 64 lanes x 2.4 GHz; two integer adds per lane per clock
-# (v_pk_add_u16 / v_add3_u32), which is also one input byte per add from LDS
-# at 128 B/clk/CU
+# Vector form of the dedispersion kernel (tile kind 1): MI355X's 256 CUs x 64
+# lanes x 2.4 GHz, two integer adds per lane per clock (v_add3_u32)
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 * 2 / 1e12
-# LDS bytes per add of the LDS-tiled kernel's interior stage for the tile shape
-# below (32 64-bit + 32 32-bit reads and at most 4 128-bit staging stores per
-# wavefront for 16384 adds: 8 channels x 2 trials x 1024 samples), against the
-# LDS rate a ds_read_b128 microbenchmark reached on MI355X (237 B per clock per
-# CU x 256 CUs x 2.4 GHz)
-LDS_BYTES_PER_ADD = {"tile": [1, 2, 8, 1, 8, 8],
-                     "bytes": (32 * 512 + 32 * 256 + 4 * 1024) / 16384}
+# Matrix-core form (tile kind 5): one v_mfma_i32_16x16x64_i8 (16384 int8 MACs,
+# 32768 ops) adds two channels into 256 samples of one trial, 512 adds: 64
+# MFMA ops per add, so the dense int8 MFMA peak of 5.0 POP/s is 78.1 T adds/s
+MFMA_OPS_PER_ADD = 64
+MFMA_PEAK_POPS = 5.0
+MFMA_PEAK_TOPS = MFMA_PEAK_POPS * 1e3 / MFMA_OPS_PER_ADD
+# LDS bytes per add of each form's interior stage, per wavefront:
+#   vector, tile [1, 2, 8, 1, 8, 8]: 32 64-bit + 32 32-bit reads and at most 4
+#   128-bit staging stores for 16384 adds (8 channels x 2 trials x 1024 samples);
+#   matrix core, tile [5, 2, 8, 1, 8, 16]: 16 (pair, trial) groups of one
+#   selection-table read and 4 data reads (128-bit each) and at most 4 128-bit
+#   staging stores for 32768 adds (16 channels x 2 trials x 1024 samples)
+# against the LDS rate of ds_read_b128 (237 B per clock per CU stored; the
+# ceiling probe's own measurement replaces it when the probe runs)
+LDS_BYTES_PER_ADD = {(1, 2, 8, 1, 8, 8): (32 * 512 + 32 * 256 + 4 * 1024) / 16384,
+                     (5, 2, 8, 1, 8, 16): (16 * 5 * 1024 + 4 * 1024) / 32768}
 LDS_PEAK_TBPS = 237 * 256 * 2.4e9 / 1e12
 # HBM bytes of one dedispersion launch of this workload, from rocprofv3 FETCH_SIZE /
 # WRITE_SIZE scaled by a copy kernel of known size (profiles/k_dedisp_lds_full_band_hbm_bytes.md).
 # Valid for the tile shape it was taken with; any other shape reports null.
-MEASURED_TRAFFIC = {"tile": [1, 2, 8, 1, 8, 8], "bytes": 61.13e9}
-# Adds per VALU instruction of the dedispersion kernel for that tile, from the
-# SQ counters (profiles/k_dedisp_lds_full_band_sq_counters.md)
-ADDS_PER_VALU = {"tile": [1, 2, 8, 1, 8, 8], "adds": 66.3}
+MEASURED_TRAFFIC = {(1, 2, 8, 1, 8, 8): 61.13e9}
+# Adds per VALU instruction of the vector form for that tile, from the SQ
+# counters (profiles/k_dedisp_lds_full_band_sq_counters.md)
+ADDS_PER_VALU = {(1, 2, 8, 1, 8, 8): 66.3}
 
 
 def log(*a):
@@ -393,6 +401,51 @@ def serve_bench(sdd, torch, nbeams: int, sat_chunks: int, rt_periods: int, max_b
     return out
 
 
+def dedisp_roofline(tile, achieved: float, ceil):
+    """Roofline of the dedispersion launch for the tile shape it ran with.
+    achieved: algorithmic adds per second (T adds/s, one per channel x trial
+    x sample)."""
+    mfma = tile[0] == 5
+    peak = MFMA_PEAK_TOPS if mfma else ALU_PEAK_TOPS
+    rf = {"bound": "mfma" if mfma else "alu", "kernel": "dedisperse", "tile": list(tile),
+          "achieved": round(achieved, 3), "peak": round(peak, 1), "unit": "TOP/s",
+          "frac": round(achieved / peak, 4), "traffic": MEASURED_TRAFFIC.get(tile)}
+    if mfma:
+        rf["peak_derivation"] = (f"dense int8 MFMA {MFMA_PEAK_POPS} POP/s / {MFMA_OPS_PER_ADD} "
+                                 "MFMA ops per add (v_mfma_i32_16x16x64_i8: 32768 ops for "
+                                 "2 channels x 256 samples)")
+        rf["mfma"] = {"achieved_pops": round(achieved * MFMA_OPS_PER_ADD / 1e3, 3),
+                      "peak_pops": MFMA_PEAK_POPS,
+                      "frac": round(achieved * MFMA_OPS_PER_ADD / 1e3 / MFMA_PEAK_POPS, 4)}
+    else:
+        rf["peak_derivation"] = "256 CUs x 64 lanes x 2.4 GHz x 2 adds (v_add3_u32)"
+    lds_bpa = LDS_BYTES_PER_ADD.get(tile)
+    lds_peak = LDS_PEAK_TBPS
+    if ceil:
+        lds_peak = ceil["ds_read_b128"]["bytes_per_clk_cu"] * 256 * 2.4e9 / 1e12
+    if lds_bpa:
+        rf["lds"] = {"bytes_per_add": round(lds_bpa, 4),
+                     "achieved": round(achieved * lds_bpa, 2), "peak": round(lds_peak, 1),
+                     "unit": "TB/s", "frac": round(achieved * lds_bpa / lds_peak, 4),
+                     "peak_source": ("ds_read_b128 rate measured by the ceiling probe" if ceil
+                                     else "stored ds_read_b128 rate")}
+    if ceil and mfma and "v_mfma_i32_16x16x64_i8" in ceil:
+        # the measured matrix-instruction rate x 512 adds per instruction
+        rate = ceil["v_mfma_i32_16x16x64_i8"]["wave_instr_per_clk_cu"]
+        ic = rate * 512 * 256 * 2.4e9 / 1e12
+        rf["issue"] = {"adds_per_mfma_instr": 512, "mfma_instr_per_clk_cu": rate,
+                       "ceiling": round(ic, 2), "unit": "TOP/s", "frac": round(achieved / ic, 4)}
+    elif ceil and tile in ADDS_PER_VALU:
+        # adds per VALU instruction (SQ counters of this tile) x the measured
+        # VOP3 issue rate
+        rate = ceil["v_add3_u32"]["wave_instr_per_clk_cu"]
+        ic = ADDS_PER_VALU[tile] * rate * 256 * 2.4e9 / 1e12
+        rf["issue"] = {"adds_per_valu_instr": ADDS_PER_VALU[tile],
+                       "valu_instr_per_clk_cu": rate, "ceiling": round(ic, 2),
+                       "unit": "TOP/s", "frac": round(achieved / ic, 4)}
+    return rf
+
+
 def probe_ceilings():
     """VALU and LDS rates of this GPU from the ceiling probe built with the
     library (paper_2605_03531_amd/probe/ceilings.hip), or None."""
@@ -577,6 +630,10 @@ def main() -> int:
     ap.add_argument("--only-multi-range", action="store_true",
                     help="run only the multi-range workload (for profiling its kernels); prints "
                          "its JSON object")
+    ap.add_argument("--only-step", action="store_true",
+                    help="run only the full-band step (no ceiling probe, no extension rows, "
+                         "no CPU baseline, serving, batch or multi-range runs: for profiling "
+                         "its kernels); prints its JSON line")
     ap.add_argument("--batch-beams", type=int, default=32)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, copy 1 GiB device-to-device three times "
@@ -598,7 +655,7 @@ def main() -> int:
                                                                args.warmup)}), flush=True)
         return 0
     # the probe runs in its own process before this one touches the GPU
-    ceil = probe_ceilings()
+    ceil = None if args.only_step else probe_ceilings()
     log(f"ceilings: {ceil}")
 
     import torch
@@ -670,44 +727,11 @@ def main() -> int:
                    "nsamp_in": T, "overlap": plan.overlap, "widths": WIDTHS,
                    "tile": list(plan.get_tile(0))},
         "stage_ms": {k: round(v[0], 4) for k, v in stage.items()},
-        "roofline": {"bound": "alu", "kernel": "dedisperse", "achieved": round(achieved, 3),
-                     "peak": round(ALU_PEAK_TOPS, 1), "unit": "TOP/s",
-                     "frac": round(achieved / ALU_PEAK_TOPS, 4),
-                     "traffic": (MEASURED_TRAFFIC["bytes"]
-                                 if list(plan.get_tile(0)) == MEASURED_TRAFFIC["tile"] else None),
-                     "lds": ({"bytes_per_add": LDS_BYTES_PER_ADD["bytes"],
-                              "achieved": round(achieved * LDS_BYTES_PER_ADD["bytes"], 2),
-                              "peak": round(LDS_PEAK_TBPS, 1), "unit": "TB/s",
-                              "frac": round(achieved * LDS_BYTES_PER_ADD["bytes"] / LDS_PEAK_TBPS,
-                                            4)}
-                             if list(plan.get_tile(0)) == LDS_BYTES_PER_ADD["tile"] else None)},
+        "roofline": None,
         "cpu_baseline": None,
         "ceilings": ceil,
     }
-    rf = res["roofline"]
-    if ceil:
-        # measured LDS rate (ds_read_b128) in place of the stored one
-        lds_peak = ceil["ds_read_b128"]["bytes_per_clk_cu"] * 256 * 2.4e9 / 1e12
-        if rf["lds"]:
-            rf["lds"]["peak"] = round(lds_peak, 1)
-            rf["lds"]["frac"] = round(rf["lds"]["achieved"] / lds_peak, 4)
-            rf["lds"]["peak_source"] = "ds_read_b128 rate measured by the ceiling probe"
-        # the kernel's own instruction-mix ceiling: adds per VALU instruction
-        # (SQ counters of this tile) x the measured VOP3 issue rate
-        if list(plan.get_tile(0)) == ADDS_PER_VALU["tile"]:
-            rate = ceil["v_add3_u32"]["wave_instr_per_clk_cu"]
-            ic = ADDS_PER_VALU["adds"] * rate * 256 * 2.4e9 / 1e12
-            rf["issue"] = {"adds_per_valu_instr": ADDS_PER_VALU["adds"],
-                           "valu_instr_per_clk_cu": rate, "ceiling": round(ic, 2),
-                           "unit": "TOP/s", "frac": round(achieved / ic, 4)}
-    res["sift"] = sift_bench(sdd, torch, plan, out, float(w.dm_list[1] - w.dm_list[0]), 1 << 16)
-    log(f"sift: {res['sift']}")
-    res["rfi"] = rfi_bench(sdd, torch, plan, xt, planes, out, ws)
-    log(f"rfi: {res['rfi']}")
-    res["robust_stats"] = robust_bench(sdd, torch, plan, xt, planes, out, ws)
-    log(f"robust statistics: {res['robust_stats']}")
-    res["ffa"] = ffa_bench(sdd, torch, planes[0], n_owned)
-    log(f"ffa: {res['ffa']}")
+    res["roofline"] = dedisp_roofline(tuple(plan.get_tile(0)), achieved, ceil)
     if args.copy_calibration:
         src = torch.empty(1 << 30, dtype=torch.uint8, device=dev).fill_(7)
         dst = torch.empty_like(src)
@@ -719,6 +743,17 @@ def main() -> int:
         log("copy calibration: 3 x 1 GiB device copies and 3 x 1 GiB elementwise "
             "(1 GiB read + 1 GiB written each)")
         del src, dst
+    if args.only_step:
+        print(json.dumps(res), flush=True)
+        return 0
+    res["sift"] = sift_bench(sdd, torch, plan, out, float(w.dm_list[1] - w.dm_list[0]), 1 << 16)
+    log(f"sift: {res['sift']}")
+    res["rfi"] = rfi_bench(sdd, torch, plan, xt, planes, out, ws)
+    log(f"rfi: {res['rfi']}")
+    res["robust_stats"] = robust_bench(sdd, torch, plan, xt, planes, out, ws)
+    log(f"robust statistics: {res['robust_stats']}")
+    res["ffa"] = ffa_bench(sdd, torch, planes[0], n_owned)
+    log(f"ffa: {res['ffa']}")
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample")
         res["cpu_baseline"] = cpu_baseline(w, plan.delays(0), args.cpu_rows)

@@ -148,10 +148,13 @@ typedef struct sdd_dm_stats {  /* moments of the owned samples of one trial */
 
 /* Tile shape of the dedispersion kernel (a fixed menu; see sdd_tile_menu).
  * kind 0: direct kernel (one thread per DM and 4 samples, no LDS);
- * kind 1..8: LDS-tiled kernel, 1 + variant flags (1: LDS stages prefetched
- * two ahead; 2: two 64-bit LDS reads per 8 samples instead of 64 + 32 bits;
- * 4: the next stage's window bases come from delays fetched a stage
- * earlier). The other fields apply to the LDS kernel. */
+ * kind 1 + flags: LDS-tiled kernel (Section 3.2's brute-force sum, staged
+ * per channel window in LDS). kind 1: vector form (byte align + widen with
+ * v_perm, two channels per v_add3 into 16-bit fields); kind 3: the same
+ * with two 64-bit LDS reads per 8 samples instead of 64 + 32 bits; kind 5:
+ * matrix-core form (the shifted channel sum as an int8 product with a 0/1
+ * selection matrix, two channels per v_mfma_i32_16x16x64_i8, int32 sums;
+ * uint8 ranges only). The other fields apply to the LDS kernels. */
 typedef struct sdd_tile {
   int32_t kind;
   int32_t dm_per_wave;     /* DM trials per wavefront */

@@ -58,6 +58,7 @@ int lds_args_for(const DedispArgs& a, LdsArgs* out) {
   const int es = a.elem_bytes;
   const int32_t flush = lds_flush_period(sh, a.max_val);
   if (es < 1 || es > 2 || flush < sh.cs) return -1;
+  if ((sh.f & 4) != 0 && es != 1) return -1;
   LdsArgs& l = *out;
   l = LdsArgs{};
   l.x = (const uint8_t*)a.x;
@@ -71,6 +72,7 @@ int lds_args_for(const DedispArgs& a, LdsArgs* out) {
   l.cols = a.cols;
   const int32_t tt = lds_tile_samples(sh, es), dt = sh.d * sh.wd;
   l.win = lds_window_bytes(tt, a.span, es);
+  if ((sh.f & 4) != 0 && 2 * sh.cs * (int64_t)l.win > 65536) return -1;
   l.n_dtiles = (a.ndm + dt - 1) / dt;
   l.n_ttiles = (int32_t)((a.cols + tt - 1) / tt);
   l.aligned = ((uintptr_t)a.x % 16 == 0) && ((a.x_pitch * es) % 16 == 0);

@@ -32,7 +32,8 @@ struct LdsShape {
   int wt;     // wavefronts along time
   int cs;     // channels per LDS stage
   int nld;    // 16-byte staging loads per thread per stage
-  int f;      // variant flags: 2 = third word through a 64-bit read
+  int f;      // variant flags: 2 = third word through a 64-bit read,
+              // 4 = matrix-core form (uint8 rows)
 };
 
 // Samples one tile of a shape covers for elements of es bytes.
@@ -42,6 +43,14 @@ inline int32_t lds_tile_samples(const LdsShape& sh, int es) { return 512 / es * 
 inline int32_t lds_flush_period(const LdsShape& sh, int32_t max_val) {
   const int32_t f = 65535 / max_val;
   return f >= 256 ? 256 : (f / sh.cs) * sh.cs;
+}
+
+// LDS bytes of one workgroup for windows of win bytes (the kernel's own
+// sizing: two stage buffers of cs windows, two copies of each in the vector
+// form; one copy and a 1 KiB selection table in the matrix-core form, whose
+// 16-bit read offsets also need 2 * cs * win <= 65536).
+inline int64_t lds_tile_bytes(const LdsShape& sh, int64_t win) {
+  return (sh.f & 4) != 0 ? 2 * (int64_t)sh.cs * win + 1024 : 4 * (int64_t)sh.cs * win;
 }
 
 extern const LdsShape kLdsShapes[];

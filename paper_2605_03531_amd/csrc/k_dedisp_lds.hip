@@ -378,19 +378,47 @@ __device__ __forceinline__ void dd_tile_impl(const LdsArgs& a, int32_t dtile, in
   }
 }
 
+#include "k_dedisp_mfma.h"
+
+// Shapes with flag 4 take the matrix-core form (uint8 rows only; its
+// launchers refuse uint16 jobs), with M 512-sample chunks = 2 M products of
+// 256 samples per trial and wavefront.
 template <int D, int M, int WD, int WT, int CS, int NLD, int F, int ES>
 __device__ __forceinline__ void dd_tile(const LdsArgs& a, int32_t dtile, int32_t ttile,
                                         uint8_t* __restrict__ lds) {
-  if (ttile < a.n_tt_interior)
-    dd_tile_impl<D, M, WD, WT, CS, NLD, F, ES, true>(a, dtile, ttile, lds);
-  else
-    dd_tile_impl<D, M, WD, WT, CS, NLD, F, ES, false>(a, dtile, ttile, lds);
+  if constexpr ((F & 4) != 0) {
+    if (ttile < a.n_tt_interior)
+      mf_tile_impl<D, 2 * M, WD, WT, CS, NLD, true>(a, dtile, ttile, lds);
+    else
+      mf_tile_impl<D, 2 * M, WD, WT, CS, NLD, false>(a, dtile, ttile, lds);
+  } else {
+    if (ttile < a.n_tt_interior)
+      dd_tile_impl<D, M, WD, WT, CS, NLD, F, ES, true>(a, dtile, ttile, lds);
+    else
+      dd_tile_impl<D, M, WD, WT, CS, NLD, F, ES, false>(a, dtile, ttile, lds);
+  }
+}
+
+// Matrix-core shapes are held to 128 VGPRs (4 wavefronts per SIMD, two
+// 512-thread workgroups per CU): left free, the persistent form's extra
+// state took its 16-channel shape to 138 (one workgroup per CU, 25%
+// slower); held, it keeps a few values in scratch and runs as fast as the
+// grid form.
+template <int F>
+constexpr int kWavesPerSimd = (F & 4) != 0 ? 4 : 1;
+
+// Dynamic LDS of one workgroup: two stage buffers of CS windows, with two
+// copies per window in the vector form, one plus the 1 KiB selection table
+// in the matrix-core form.
+template <int CS, int F>
+constexpr size_t tile_lds_bytes(int32_t win) {
+  return (F & 4) != 0 ? (size_t)2 * CS * win + 1024 : (size_t)2 * CS * 2 * win;
 }
 
 // Grid form: one workgroup per tile of one job, ordered time-tile-major with a
 // contiguous run of tiles per XCD (workgroups go to the 8 XCDs round-robin).
 template <int D, int M, int WD, int WT, int CS, int NLD, int F, int ES>
-__global__ __launch_bounds__(64 * WD * WT) void k_dedisp_lds(LdsArgs a) {
+__global__ __launch_bounds__(64 * WD * WT, kWavesPerSimd<F>) void k_dedisp_lds(LdsArgs a) {
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
   const int32_t nblk = a.n_dtiles * a.n_ttiles;
   const int32_t b = blockIdx.x;
@@ -410,7 +438,7 @@ __global__ __launch_bounds__(64 * WD * WT) void k_dedisp_lds(LdsArgs a) {
 // tile r * n + k to workgroup k in round r, lets the workgroups drift apart
 // by many rounds over a long batch and loses that sharing.)
 template <int D, int M, int WD, int WT, int CS, int NLD, int F, int ES>
-__global__ __launch_bounds__(64 * WD * WT) void k_dedisp_lds_multi(MultiArgs m) {
+__global__ __launch_bounds__(64 * WD * WT, kWavesPerSimd<F>) void k_dedisp_lds_multi(MultiArgs m) {
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
   __shared__ int32_t ticket;
   const int32_t total = m.tile_base[m.njobs];
@@ -436,7 +464,8 @@ __global__ __launch_bounds__(64 * WD * WT) void k_dedisp_lds_multi(MultiArgs m) 
 template <int D, int M, int WD, int WT, int CS, int NLD, int F, int ES>
 hipError_t launch_multi(const MultiArgs& m, int32_t max_win, hipStream_t s) {
   constexpr int NT = 64 * WD * WT;
-  const size_t lds = (size_t)2 * CS * 2 * max_win;
+  if ((F & 4) != 0 && ES != 1) return hipErrorInvalidValue;
+  const size_t lds = tile_lds_bytes<CS, F>(max_win);
   auto kern = k_dedisp_lds_multi<D, M, WD, WT, CS, NLD, F, ES>;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
@@ -459,7 +488,8 @@ hipError_t launch_multi(const MultiArgs& m, int32_t max_win, hipStream_t s) {
 template <int D, int M, int WD, int WT, int CS, int NLD, int F, int ES>
 hipError_t launch_one(const LdsArgs& a, hipStream_t s) {
   constexpr int NT = 64 * WD * WT;
-  const size_t lds = (size_t)2 * CS * 2 * a.win;
+  if ((F & 4) != 0 && ES != 1) return hipErrorInvalidValue;
+  const size_t lds = tile_lds_bytes<CS, F>(a.win);
   auto kern = k_dedisp_lds<D, M, WD, WT, CS, NLD, F, ES>;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
@@ -476,6 +506,8 @@ hipError_t launch_one(const LdsArgs& a, hipStream_t s) {
 // The built menu, {D, M, WD, WT, CS, NLD, F}; sdd_tile carries it as
 // {kind 1 + F, D, WD, WT, pairs per lane = 4*M, CS}.
 #define SDD_LDS_SHAPES(X)      \
+  X(2, 2, 8, 1, 16, 4, 4)      \
+  X(2, 2, 8, 1, 8, 2, 4)       \
   X(2, 2, 8, 1, 8, 2, 0)       \
   X(2, 2, 8, 1, 4, 1, 0)       \
   X(2, 2, 8, 1, 4, 1, 2)       \

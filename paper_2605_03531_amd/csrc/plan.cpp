@@ -115,11 +115,13 @@ sdd_status check_tile_fits(const sdd_plan* p, int32_t r, const sdd_tile& t, int3
   for (size_t i = 1; i < R.dms.size(); ++i)
     if (R.dms[i] < R.dms[i - 1])
       SDD_FAIL(SDD_EINVAL, "range %d: the LDS kernel needs ascending trial DMs", r);
+  if ((sh.f & 4) != 0 && es != 1)
+    SDD_FAIL(SDD_EINVAL, "range %d: the matrix-core tile takes uint8 rows (decimation 1) only", r);
   const int32_t dt = sh.d * sh.wd, tt = lds_tile_samples(sh, es), nt = 64 * sh.wd * sh.wt;
   const int32_t span = range_span(p, r, dt);
   const int64_t win = lds_window_bytes(tt, span, es);
-  const int64_t lds = 4 * (int64_t)sh.cs * win;
-  if (lds > 160 * 1024)
+  const int64_t lds = lds_tile_bytes(sh, win);
+  if (lds > 160 * 1024 || ((sh.f & 4) != 0 && 2 * sh.cs * win > 65536))
     SDD_FAIL(SDD_EINVAL, "range %d: delay span %d needs %lld bytes of LDS for this tile", r, span,
              (long long)lds);
   if ((int64_t)sh.cs * (win / 16) > (int64_t)sh.nld * nt)

@@ -1,8 +1,8 @@
-// Measured VALU and LDS ceilings of the GPU it runs on (one process, one
-// device): the rates the dedispersion kernel's roofline lines are taken
-// against. Each kernel runs 512-thread workgroups (8 wavefronts), a grid of
-// 2048 workgroups, and loops over blocks of 8 independent instructions of one
-// kind followed by a wait, so every wavefront keeps 8 in flight and each CU
+// Measured VALU, LDS and matrix-core ceilings of the GPU it runs on (one
+// process, one device): the rates the dedispersion kernels' roofline lines are
+// taken against. Each kernel runs 512-thread workgroups (8 wavefronts), a grid
+// of 2048 workgroups, and loops over blocks of 8 independent instructions of
+// one kind (the memory ones followed by a wait), so every wavefront keeps 8 in flight and each CU
 // holds 16 or more wavefronts. Rates are wavefront-instructions per clock per
 // CU at the device's maximum clock (so a slower sustained clock reads as a
 // lower rate) and bytes per clock per CU for the memory instructions.
@@ -118,6 +118,25 @@ __global__ __launch_bounds__(kNt) void k_valu(uint32_t* out) {
   out[blockIdx.x * kNt + threadIdx.x] = a0 ^ a1 ^ a2 ^ a3 ^ a4 ^ a5 ^ a6 ^ a7;
 }
 
+// 8 independent accumulator chains of v_mfma_i32_16x16x64_i8 (the matrix
+// instruction of the matrix-core dedispersion).
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(kNt) void k_mfma(uint32_t* out) {
+  const int l = threadIdx.x & 63;
+  const i32x4 a = {l, 3 * l, 5 * l, 7 * l}, b = {11 * l, l, 2 * l, 9 * l};
+  i32x4 acc[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) acc[k] = i32x4{k, 0, 0, 0};
+  for (int it = 0; it < kIter; ++it) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc[k] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, acc[k], 0, 0, 0);
+  }
+  i32x4 s = acc[0];
+#pragma unroll
+  for (int k = 1; k < 8; ++k) s ^= acc[k];
+  out[blockIdx.x * kNt + threadIdx.x] = (uint32_t)(s.x ^ s.y ^ s.z ^ s.w);
+}
+
 template <typename F>
 float time_ms(F f) {
   hipEvent_t e0, e1;
@@ -158,6 +177,7 @@ int main() {
       {"ds_write_b128", time_ms([&] { hipLaunchKernelGGL(k_wr128, dim3(kGrid), dim3(kNt), 0, 0, out); }), 16},
       {"v_add3_u32", time_ms([&] { hipLaunchKernelGGL(k_valu<false>, dim3(kGrid), dim3(kNt), 0, 0, out); }), 0},
       {"v_perm_b32", time_ms([&] { hipLaunchKernelGGL(k_valu<true>, dim3(kGrid), dim3(kNt), 0, 0, out); }), 0},
+      {"v_mfma_i32_16x16x64_i8", time_ms([&] { hipLaunchKernelGGL(k_mfma, dim3(kGrid), dim3(kNt), 0, 0, out); }), 0},
   };
   if (hipDeviceSynchronize() != hipSuccess) {
     std::fprintf(stderr, "device error\n");
