@@ -52,11 +52,12 @@ LDS_BYTES_PER_ADD = {(1, 2, 8, 1, 8, 8): (32 * 512 + 32 * 256 + 4 * 1024) / 1638
                      (5, 2, 8, 1, 8, 16): (16 * 5 * 1024 + 4 * 1024) / 32768}
 LDS_PEAK_TBPS = 237 * 256 * 2.4e9 / 1e12
 # HBM bytes of one dedispersion launch of this workload, from rocprofv3 FETCH_SIZE /
-# WRITE_SIZE scaled by a copy kernel of known size (profiles/k_dedisp_lds_full_band_hbm_bytes.md).
+# WRITE_SIZE scaled by a copy kernel of known size (profiles/k_dedisp_vector_full_band_hbm_bytes.md,
+# profiles/k_dedisp_mfma_full_band_hbm_bytes.md).
 # Valid for the tile shape it was taken with; any other shape reports null.
-MEASURED_TRAFFIC = {(1, 2, 8, 1, 8, 8): 61.13e9}
+MEASURED_TRAFFIC = {(1, 2, 8, 1, 8, 8): 61.13e9, (5, 2, 8, 1, 8, 16): 52.34e9}
 # Adds per VALU instruction of the vector form for that tile, from the SQ
-# counters (profiles/k_dedisp_lds_full_band_sq_counters.md)
+# counters (profiles/k_dedisp_vector_full_band_sq_counters.md)
 ADDS_PER_VALU = {(1, 2, 8, 1, 8, 8): 66.3}
 
 
@@ -634,6 +635,9 @@ def main() -> int:
                     help="run only the full-band step (no ceiling probe, no extension rows, "
                          "no CPU baseline, serving, batch or multi-range runs: for profiling "
                          "its kernels); prints its JSON line")
+    ap.add_argument("--tile", default="",
+                    help="dedispersion tile of the full-band step as kind,D,WD,WT,pairs,CS "
+                         "(default: the plan's choice, the first fitting menu shape)")
     ap.add_argument("--batch-beams", type=int, default=32)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, copy 1 GiB device-to-device three times "
@@ -672,6 +676,8 @@ def main() -> int:
     w = synth.full_band(delay_fn, widths=WIDTHS)
     plan = sdd.Plan(w.freqs_mhz, w.t_samp, dm_list=w.dm_list, widths=WIDTHS, cand_block=1024,
                     threshold=7.0, layout="time")
+    if args.tile:
+        plan.set_tile(tuple(int(v) for v in args.tile.split(",")))
     T = w.nsamp
     g = plan.geometry(T)
     n_owned = g["n_owned"]
