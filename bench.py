@@ -227,6 +227,41 @@ def rfi_bench(sdd, torch, plan, xt, planes, out, ws_unused, reps: int = 3):
             "pre_corner_turn_ms": round(ms.value / max(n.value, 1), 4)}
 
 
+def forms_bench(sdd, torch, plan, xt, planes, out, ws, reps: int = 3):
+    """The dedispersion stage of the step's chunk with each form of the LDS
+    kernel: the matrix-core tile (the default) and the vector tile, and
+    whether their planes are identical."""
+    import ctypes as C
+    from paper_2605_03531_amd import _capi as A
+    L = A.lib()
+    units = plan.nchan * plan.ndm_total * plan.geometry(xt.shape[0])["n_owned"]
+    keep = tuple(plan.get_tile(0))
+    res, ref = {}, None
+    for name, tile in (("matrix_core", (5, 2, 8, 1, 8, 16)), ("vector", (1, 2, 8, 1, 8, 8))):
+        plan.set_tile(tile)
+        plan.dedisperse_search(xt, planes=planes, out=out, workspace=ws)
+        torch.cuda.synchronize()
+        A.check(L.sdd_profile_enable(1), "profile")
+        for _ in range(reps):
+            plan.dedisperse_search(xt, planes=planes, out=out, workspace=ws)
+        torch.cuda.synchronize()
+        ms, n = C.c_double(), C.c_int64()
+        A.check(L.sdd_profile_read(A.STAGES["dedisperse"], C.byref(ms), C.byref(n)), "read")
+        L.sdd_profile_enable(0)
+        t = ms.value / max(n.value, 1)
+        same = None
+        if ref is None:
+            ref = planes[0].clone()
+        else:
+            same = bool(torch.equal(ref, planes[0]))
+        res[name] = {"tile": list(tile), "dedisperse_ms": round(t, 3),
+                     "adds_per_s": round(units / t / 1e9, 2), "unit": "T adds/s",
+                     "plane_equal_to_matrix_core": same}
+    plan.set_tile(keep)
+    del ref
+    return res
+
+
 def robust_bench(sdd, torch, plan, xt, planes, out, ws, reps: int = 3):
     """Search-stage time with each noise estimate, and with running-median
     de-reddening (256-sample blocks, 1280-sample window) (the step's chunk)."""
@@ -752,6 +787,8 @@ def main() -> int:
     if args.only_step:
         print(json.dumps(res), flush=True)
         return 0
+    res["dedisperse_forms"] = forms_bench(sdd, torch, plan, xt, planes, out, ws)
+    log(f"dedispersion forms: {res['dedisperse_forms']}")
     res["sift"] = sift_bench(sdd, torch, plan, out, float(w.dm_list[1] - w.dm_list[0]), 1 << 16)
     log(f"sift: {res['sift']}")
     res["rfi"] = rfi_bench(sdd, torch, plan, xt, planes, out, ws)

@@ -72,7 +72,6 @@ int lds_args_for(const DedispArgs& a, LdsArgs* out) {
   l.cols = a.cols;
   const int32_t tt = lds_tile_samples(sh, es), dt = sh.d * sh.wd;
   l.win = lds_window_bytes(tt, a.span, es);
-  if ((sh.f & 4) != 0 && 2 * sh.cs * (int64_t)l.win > 65536) return -1;
   l.n_dtiles = (a.ndm + dt - 1) / dt;
   l.n_ttiles = (int32_t)((a.cols + tt - 1) / tt);
   l.aligned = ((uintptr_t)a.x % 16 == 0) && ((a.x_pitch * es) % 16 == 0);

@@ -47,8 +47,7 @@ inline int32_t lds_flush_period(const LdsShape& sh, int32_t max_val) {
 
 // LDS bytes of one workgroup for windows of win bytes (the kernel's own
 // sizing: two stage buffers of cs windows, two copies of each in the vector
-// form; one copy and a 1 KiB selection table in the matrix-core form, whose
-// 16-bit read offsets also need 2 * cs * win <= 65536).
+// form; one copy and a 1 KiB selection table in the matrix-core form).
 inline int64_t lds_tile_bytes(const LdsShape& sh, int64_t win) {
   return (sh.f & 4) != 0 ? 2 * (int64_t)sh.cs * win + 1024 : 4 * (int64_t)sh.cs * win;
 }

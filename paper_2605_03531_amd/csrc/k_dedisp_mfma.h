@@ -139,8 +139,8 @@ __device__ __forceinline__ void mf_tile_impl(const LdsArgs& a, int32_t dtile, in
   };
 
   // ---- read positions: lane k < NE holds entry k = pair * D + d ----
-  // PP: LDS byte offsets (stage buffer, slot, 16-aligned window offset) of
-  // the pair's two channels in the low and high halves; RR: 16 * r of each.
+  // PP: LDS offsets / 16 (stage buffer, slot, 16-aligned window offset) of
+  // the pair's two channels in the low and high halves; RR: r of each.
   uint32_t dlA, dlA0, dlB, dlB0;
   {
     const int32_t k = lane < NE ? lane : 0;
@@ -164,8 +164,9 @@ __device__ __forceinline__ void mf_tile_impl(const LdsArgs& a, int32_t dtile, in
   auto pack_words = [&](int32_t s, uint32_t& pp, uint32_t& rr) {
     const int32_t oA = wA - (wA0 & ~15), oB = wB - (wB0 & ~15);
     const int32_t bo = (s & 1) * buf + pA * win;
-    pp = (uint32_t)(bo + (oA & ~15)) | ((uint32_t)(bo + win + (oB & ~15)) << 16);
-    rr = (uint32_t)(16 * (oA & 15)) | ((uint32_t)(16 * (oB & 15)) << 16);
+    // offsets in 16-byte units (every one is 16-aligned): 16 bits hold 1 MiB
+    pp = (uint32_t)((bo + (oA & ~15)) >> 4) | ((uint32_t)((bo + win + (oB & ~15)) >> 4) << 16);
+    rr = (uint32_t)(oA & 15) | ((uint32_t)(oB & 15) << 16);
   };
 
   // lane constants: column n, K group g = 2 q + h
@@ -181,8 +182,8 @@ __device__ __forceinline__ void mf_tile_impl(const LdsArgs& a, int32_t dtile, in
   auto fetch = [&](uint32_t ppv, uint32_t rrv, int e, Grp& r) {
     const uint32_t pp = (uint32_t)__builtin_amdgcn_readlane((int)ppv, e);
     const uint32_t rr = (uint32_t)__builtin_amdgcn_readlane((int)rrv, e);
-    const uint32_t ab = __builtin_amdgcn_ubfe(pp, lane_sh, 16) + lane_b;
-    const uint32_t at = __builtin_amdgcn_ubfe(rr, lane_sh, 16) + lane_t;
+    const uint32_t ab = (__builtin_amdgcn_ubfe(pp, lane_sh, 16) << 4) + lane_b;
+    const uint32_t at = (__builtin_amdgcn_ubfe(rr, lane_sh, 16) << 4) + lane_t;
     r.sel = *reinterpret_cast<const i32x4*>(lds + at);
 #pragma unroll
     for (int m = 0; m < MT; ++m) r.x[m] = *reinterpret_cast<const i32x4*>(lds + ab + 256 * m);

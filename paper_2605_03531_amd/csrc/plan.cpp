@@ -121,7 +121,7 @@ sdd_status check_tile_fits(const sdd_plan* p, int32_t r, const sdd_tile& t, int3
   const int32_t span = range_span(p, r, dt);
   const int64_t win = lds_window_bytes(tt, span, es);
   const int64_t lds = lds_tile_bytes(sh, win);
-  if (lds > 160 * 1024 || ((sh.f & 4) != 0 && 2 * sh.cs * win > 65536))
+  if (lds > 160 * 1024)
     SDD_FAIL(SDD_EINVAL, "range %d: delay span %d needs %lld bytes of LDS for this tile", r, span,
              (long long)lds);
   if ((int64_t)sh.cs * (win / 16) > (int64_t)sh.nld * nt)
