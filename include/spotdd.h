@@ -154,7 +154,10 @@ typedef struct sdd_dm_stats {  /* moments of the owned samples of one trial */
  * with two 64-bit LDS reads per 8 samples instead of 64 + 32 bits; kind 5:
  * matrix-core form (the shifted channel sum as an int8 product with a 0/1
  * selection matrix, two channels per v_mfma_i32_16x16x64_i8, int32 sums;
- * uint8 ranges only). The other fields apply to the LDS kernels. */
+ * uint8 ranges only); kind 21: kind 5 that reads a channel pair's data words
+ * once for two neighbouring trials when both windows start in the same
+ * 16-byte words (the default for ranges with fine DM steps, where most
+ * groups do). The other fields apply to the LDS kernels. */
 typedef struct sdd_tile {
   int32_t kind;
   int32_t dm_per_wave;     /* DM trials per wavefront */

@@ -33,7 +33,8 @@ struct LdsShape {
   int cs;     // channels per LDS stage
   int nld;    // 16-byte staging loads per thread per stage
   int f;      // variant flags: 2 = third word through a 64-bit read,
-              // 4 = matrix-core form (uint8 rows)
+              // 4 = matrix-core form (uint8 rows), 4 | 16 = matrix-core form
+              // that skips the data reads neighbouring trials share
 };
 
 // Samples one tile of a shape covers for elements of es bytes.
@@ -51,6 +52,11 @@ inline int32_t lds_flush_period(const LdsShape& sh, int32_t max_val) {
 inline int64_t lds_tile_bytes(const LdsShape& sh, int64_t win) {
   return (sh.f & 4) != 0 ? 2 * (int64_t)sh.cs * win + 1024 : 4 * (int64_t)sh.cs * win;
 }
+
+// Sharing matrix-core shapes (flag 16) are the default for a range when at
+// least this fraction of its (channel pair, trial pair) groups read the same
+// data words for both trials.
+constexpr double kShareThreshold = 0.5;
 
 extern const LdsShape kLdsShapes[];
 extern const int kNumLdsShapes;

@@ -387,10 +387,11 @@ template <int D, int M, int WD, int WT, int CS, int NLD, int F, int ES>
 __device__ __forceinline__ void dd_tile(const LdsArgs& a, int32_t dtile, int32_t ttile,
                                         uint8_t* __restrict__ lds) {
   if constexpr ((F & 4) != 0) {
+    constexpr bool SHARE = (F & 16) != 0;
     if (ttile < a.n_tt_interior)
-      mf_tile_impl<D, 2 * M, WD, WT, CS, NLD, true>(a, dtile, ttile, lds);
+      mf_tile_impl<D, 2 * M, WD, WT, CS, NLD, true, SHARE>(a, dtile, ttile, lds);
     else
-      mf_tile_impl<D, 2 * M, WD, WT, CS, NLD, false>(a, dtile, ttile, lds);
+      mf_tile_impl<D, 2 * M, WD, WT, CS, NLD, false, SHARE>(a, dtile, ttile, lds);
   } else {
     if (ttile < a.n_tt_interior)
       dd_tile_impl<D, M, WD, WT, CS, NLD, F, ES, true>(a, dtile, ttile, lds);
@@ -508,6 +509,7 @@ hipError_t launch_one(const LdsArgs& a, hipStream_t s) {
 #define SDD_LDS_SHAPES(X)      \
   X(2, 2, 8, 1, 16, 4, 4)      \
   X(2, 2, 8, 1, 8, 2, 4)       \
+  X(2, 2, 8, 1, 8, 2, 20)      \
   X(2, 2, 8, 1, 8, 2, 0)       \
   X(2, 2, 8, 1, 4, 1, 0)       \
   X(2, 2, 8, 1, 4, 1, 2)       \

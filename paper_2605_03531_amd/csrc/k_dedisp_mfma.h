@@ -28,7 +28,7 @@
 
 typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
 
-template <int D, int MT, int WD, int WT, int CS, int NLD, bool INTERIOR>
+template <int D, int MT, int WD, int WT, int CS, int NLD, bool INTERIOR, bool SHARE>
 __device__ __forceinline__ void mf_tile_impl(const LdsArgs& a, int32_t dtile, int32_t ttile,
                                              uint8_t* __restrict__ lds) {
   constexpr int NT = 64 * WD * WT;
@@ -215,12 +215,61 @@ __device__ __forceinline__ void mf_tile_impl(const LdsArgs& a, int32_t dtile, in
       load_words(s + 1);
       if (s + 2 < nstages) load_bases(s + 2, bnext);
     }
-    Grp gr[2];
-    fetch(ppc, rrc, 0, gr[0]);
+    if constexpr (SHARE) {
+      // Trials of one wavefront are neighbours: when a channel pair's two
+      // windows start in the same 16-byte words for trial d as for trial
+      // d - 1 (equal packed offsets), the data operands are the same and
+      // only the selection differs, so the data reads are skipped.
+      constexpr int NP = CS / 2;
+      struct Pair {
+        uint32_t pp[D];
+        i32x4 sel[D];
+        i32x4 x[MT];
+      };
+      auto fetch_pair = [&](int p, Pair& r) {
 #pragma unroll
-    for (int e = 0; e < NE; ++e) {
-      if (e + 1 < NE) fetch(ppc, rrc, e + 1, gr[(e + 1) & 1]);
-      consume(e, gr[e & 1]);
+        for (int d = 0; d < D; ++d) {
+          r.pp[d] = (uint32_t)__builtin_amdgcn_readlane((int)ppc, p * D + d);
+          const uint32_t rr = (uint32_t)__builtin_amdgcn_readlane((int)rrc, p * D + d);
+          const uint32_t at = (__builtin_amdgcn_ubfe(rr, lane_sh, 16) << 4) + lane_t;
+          r.sel[d] = *reinterpret_cast<const i32x4*>(lds + at);
+        }
+        const uint32_t ab = (__builtin_amdgcn_ubfe(r.pp[0], lane_sh, 16) << 4) + lane_b;
+#pragma unroll
+        for (int m = 0; m < MT; ++m) r.x[m] = *reinterpret_cast<const i32x4*>(lds + ab + 256 * m);
+      };
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        Pair c;
+        fetch_pair(p, c);
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+          acc[0][m] = __builtin_amdgcn_mfma_i32_16x16x64_i8(c.sel[0], c.x[m], acc[0][m], 0, 0, 0);
+#pragma unroll
+        for (int d = 1; d < D; ++d) {
+          if (c.pp[d] == c.pp[0]) {
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+              acc[d][m] = __builtin_amdgcn_mfma_i32_16x16x64_i8(c.sel[d], c.x[m], acc[d][m], 0, 0, 0);
+          } else {
+            const uint32_t ab = (__builtin_amdgcn_ubfe(c.pp[d], lane_sh, 16) << 4) + lane_b;
+            i32x4 y[MT];
+#pragma unroll
+            for (int m = 0; m < MT; ++m) y[m] = *reinterpret_cast<const i32x4*>(lds + ab + 256 * m);
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+              acc[d][m] = __builtin_amdgcn_mfma_i32_16x16x64_i8(c.sel[d], y[m], acc[d][m], 0, 0, 0);
+          }
+        }
+      }
+    } else {
+      Grp gr[2];
+      fetch(ppc, rrc, 0, gr[0]);
+#pragma unroll
+      for (int e = 0; e < NE; ++e) {
+        if (e + 1 < NE) fetch(ppc, rrc, e + 1, gr[(e + 1) & 1]);
+        consume(e, gr[e & 1]);
+      }
     }
     if (s + 1 < nstages) {
       store_stage(s + 1);

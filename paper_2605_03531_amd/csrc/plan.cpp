@@ -130,11 +130,47 @@ sdd_status check_tile_fits(const sdd_plan* p, int32_t r, const sdd_tile& t, int3
   return SDD_OK;
 }
 
+// Fraction of (channel pair, neighbouring trial pair) groups of a range
+// whose two trials read the same 16-byte words of the staged windows, with
+// the matrix-core tiling (DM tiles of dt trials, wavefronts owning trials
+// 2w, 2w + 1 of a tile, channels in pairs): the data reads the sharing form
+// of the matrix-core kernel skips.
+double range_share_fraction(const sdd_plan* p, int32_t r, int32_t dt) {
+  const Range& R = p->ranges[r];
+  const int32_t ndm = R.ndm(), C = p->nchan;
+  int64_t groups = 0, shared = 0;
+  for (int32_t i = 0; i + 1 < ndm; i += 2) {
+    const int32_t i0 = i / dt * dt;
+    if (i + 1 >= i0 + dt) continue;
+    const int32_t* a = &R.delays[(size_t)i * C];
+    const int32_t* b = &R.delays[(size_t)(i + 1) * C];
+    const int32_t* z = &R.delays[(size_t)i0 * C];
+    for (int32_t c = 0; c + 1 < C; c += 2) {
+      const int32_t pa0 = (a[c] - (z[c] & ~15)) & ~15, pb0 = (b[c] - (z[c] & ~15)) & ~15;
+      const int32_t pa1 = (a[c + 1] - (z[c + 1] & ~15)) & ~15;
+      const int32_t pb1 = (b[c + 1] - (z[c + 1] & ~15)) & ~15;
+      shared += (pa0 == pb0 && pa1 == pb1);
+      ++groups;
+    }
+  }
+  return groups ? (double)shared / (double)groups : 0.0;
+}
+
 sdd_tile default_tile(const sdd_plan* p, int32_t r, int32_t* span_out) {
-  // the first LDS shape of the menu that fits (the menu is in preference
-  // order), else the direct kernel
+  // The first LDS shape of the menu that fits (the menu is in preference
+  // order), else the direct kernel. Shapes of the sharing matrix-core form
+  // (flag 16) come first when at least half of the range's groups share
+  // their data reads (fine DM steps), and are skipped otherwise.
+  bool share = false;
+  for (int k = 0; k < kNumLdsShapes && !share; ++k) {
+    const LdsShape& sh = kLdsShapes[k];
+    if ((sh.f & 16) != 0)
+      share = range_share_fraction(p, r, sh.d * sh.wd) >= kShareThreshold;
+  }
+  for (int pass = share ? 0 : 1; pass < 2; ++pass)
   for (int k = 0; k < kNumLdsShapes; ++k) {
     const LdsShape& sh = kLdsShapes[k];
+    if (((sh.f & 16) != 0) != (pass == 0)) continue;
     sdd_tile t{1 + sh.f, sh.d, sh.wd, sh.wt, 4 * sh.m, sh.cs};
     int32_t span = 0;
     if (check_tile_fits(p, r, t, &span) == SDD_OK) {

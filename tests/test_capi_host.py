@@ -318,3 +318,40 @@ def test_misaligned_workspaces_are_refused():
     d = A.SiftDesc()
     assert L.sdd_sift_candidates(p.handle, fake, fake, 16, C.byref(d), fake, fake, None,
                                  fake + 64, nb.value, None) == A.SDD_EINVAL
+
+
+def _share_fraction(d, dt=16):
+    """Groups (channel pair, trial pair 2w, 2w+1 of a DM tile) whose two
+    trials start in the same 16-byte words of the windows, from the delay
+    table (numpy, independent of the library)."""
+    d = np.asarray(d, dtype=np.int64)
+    ndm, nchan = d.shape
+    shared = total = 0
+    for i in range(0, ndm - 1, 2):
+        i0 = i // dt * dt
+        if i + 1 >= i0 + dt:
+            continue
+        base = d[i0] & ~15
+        pa = (d[i] - base) & ~15
+        pb = (d[i + 1] - base) & ~15
+        same = pa == pb
+        pairs = same[0:nchan - 1:2] & same[1::2]
+        shared += int(pairs.sum())
+        total += pairs.size
+    return shared / total
+
+
+def test_default_tiles_by_range():
+    """The plan's default tile per range: the matrix-core form for uint8
+    ranges, its read-sharing variant where at least half of the groups of
+    neighbouring trials start in the same data words (fine DM steps), the
+    vector form for decimated (uint16) ranges."""
+    f = np.linspace(750.0, 550.0, 4096)
+    coarse = sdd.Plan(f, 81.92e-6, dm_list=np.linspace(0.0, 1000.0, 2048))
+    assert _share_fraction(coarse.delays(0)) < 0.5
+    assert coarse.get_tile(0) == (5, 2, 8, 1, 8, 16)
+    multi = sdd.Plan(f, 81.92e-6, ranges=synth.MULTI_RANGES)
+    assert _share_fraction(multi.delays(0)) >= 0.5
+    assert multi.get_tile(0) == (21, 2, 8, 1, 8, 8)
+    for r in range(1, len(synth.MULTI_RANGES)):
+        assert multi.get_tile(r)[0] == 1
