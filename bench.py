@@ -43,12 +43,15 @@ MFMA_PEAK_TOPS = MFMA_PEAK_POPS * 1e3 / MFMA_OPS_PER_ADD
 # LDS bytes per add of each form's interior stage, per wavefront:
 #   vector, tile [1, 2, 8, 1, 8, 8]: 32 64-bit + 32 32-bit reads and at most 4
 #   128-bit staging stores for 16384 adds (8 channels x 2 trials x 1024 samples);
-#   matrix core, tile [5, 2, 8, 1, 8, 16]: 16 (pair, trial) groups of one
-#   selection-table read and 4 data reads (128-bit each) and at most 4 128-bit
-#   staging stores for 32768 adds (16 channels x 2 trials x 1024 samples)
+#   matrix core, tile [5, 1, 16, 1, 16, 16]: 8 (pair, trial) groups of one
+#   selection-table read and 8 data reads (128-bit each) and at most 3 128-bit
+#   staging stores for 32768 adds (16 channels x 1 trial x 2048 samples);
+#   tile [5, 2, 8, 1, 8, 16]: 16 groups of one table read and 4 data reads and
+#   at most 4 staging stores for 32768 adds (16 channels x 2 trials x 1024)
 # against the LDS rate of ds_read_b128 (237 B per clock per CU stored; the
 # ceiling probe's own measurement replaces it when the probe runs)
 LDS_BYTES_PER_ADD = {(1, 2, 8, 1, 8, 8): (32 * 512 + 32 * 256 + 4 * 1024) / 16384,
+                     (5, 1, 16, 1, 16, 16): (8 * 9 * 1024 + 3 * 1024) / 32768,
                      (5, 2, 8, 1, 8, 16): (16 * 5 * 1024 + 4 * 1024) / 32768}
 LDS_PEAK_TBPS = 237 * 256 * 2.4e9 / 1e12
 # HBM bytes of one dedispersion launch of this workload, from rocprofv3 FETCH_SIZE /
@@ -229,15 +232,16 @@ def rfi_bench(sdd, torch, plan, xt, planes, out, ws_unused, reps: int = 3):
 
 def forms_bench(sdd, torch, plan, xt, planes, out, ws, reps: int = 3):
     """The dedispersion stage of the step's chunk with each form of the LDS
-    kernel: the matrix-core tile (the default) and the vector tile, and
-    whether their planes are identical."""
+    kernel: the matrix-core tile (the plan's default) and the vector tile,
+    and whether their planes are identical."""
     import ctypes as C
     from paper_2605_03531_amd import _capi as A
     L = A.lib()
     units = plan.nchan * plan.ndm_total * plan.geometry(xt.shape[0])["n_owned"]
     keep = tuple(plan.get_tile(0))
     res, ref = {}, None
-    for name, tile in (("matrix_core", (5, 2, 8, 1, 8, 16)), ("vector", (1, 2, 8, 1, 8, 8))):
+    mtile = keep if keep[0] in (5, 21) else (5, 1, 16, 1, 16, 16)
+    for name, tile in (("matrix_core", mtile), ("vector", (1, 2, 8, 1, 8, 8))):
         plan.set_tile(tile)
         plan.dedisperse_search(xt, planes=planes, out=out, workspace=ws)
         torch.cuda.synchronize()

@@ -507,6 +507,7 @@ hipError_t launch_one(const LdsArgs& a, hipStream_t s) {
 // The built menu, {D, M, WD, WT, CS, NLD, F}; sdd_tile carries it as
 // {kind 1 + F, D, WD, WT, pairs per lane = 4*M, CS}.
 #define SDD_LDS_SHAPES(X)      \
+  X(1, 4, 16, 1, 16, 3, 4)     \
   X(2, 2, 8, 1, 16, 4, 4)      \
   X(2, 2, 8, 1, 8, 2, 4)       \
   X(2, 2, 8, 1, 8, 2, 20)      \

@@ -349,7 +349,7 @@ def test_default_tiles_by_range():
     f = np.linspace(750.0, 550.0, 4096)
     coarse = sdd.Plan(f, 81.92e-6, dm_list=np.linspace(0.0, 1000.0, 2048))
     assert _share_fraction(coarse.delays(0)) < 0.5
-    assert coarse.get_tile(0) == (5, 2, 8, 1, 8, 16)
+    assert coarse.get_tile(0) == (5, 1, 16, 1, 16, 16)
     multi = sdd.Plan(f, 81.92e-6, ranges=synth.MULTI_RANGES)
     assert _share_fraction(multi.delays(0)) >= 0.5
     assert multi.get_tile(0) == (21, 2, 8, 1, 8, 8)
