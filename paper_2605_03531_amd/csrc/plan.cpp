@@ -160,7 +160,23 @@ sdd_tile default_tile(const sdd_plan* p, int32_t r, int32_t* span_out) {
   // The first LDS shape of the menu that fits (the menu is in preference
   // order), else the direct kernel. Shapes of the sharing matrix-core form
   // (flag 16) come first when at least half of the range's groups share
-  // their data reads (fine DM steps), and are skipped otherwise.
+  // their data reads (fine DM steps), and are skipped otherwise; decimated
+  // ranges try the vector form's 4-channel-stage shape first.
+  const Range& R = p->ranges[r];
+  if (R.dec > 1) {
+    // uint16 rows: the vector form with 4-channel stages first (7-9% faster
+    // than 8-channel stages on the decimated ranges of the multi-range plan)
+    for (int k = 0; k < kNumLdsShapes; ++k) {
+      const LdsShape& sh = kLdsShapes[k];
+      if (sh.f != 0 || sh.d != 2 || sh.m != 2 || sh.wd != 8 || sh.wt != 1 || sh.cs != 4) continue;
+      sdd_tile t{1, sh.d, sh.wd, sh.wt, 4 * sh.m, sh.cs};
+      int32_t span = 0;
+      if (check_tile_fits(p, r, t, &span) == SDD_OK) {
+        *span_out = span;
+        return t;
+      }
+    }
+  }
   bool share = false;
   for (int k = 0; k < kNumLdsShapes && !share; ++k) {
     const LdsShape& sh = kLdsShapes[k];

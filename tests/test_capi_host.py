@@ -345,7 +345,7 @@ def test_default_tiles_by_range():
     """The plan's default tile per range: the matrix-core form for uint8
     ranges, its read-sharing variant where at least half of the groups of
     neighbouring trials start in the same data words (fine DM steps), the
-    vector form for decimated (uint16) ranges."""
+    vector form with 4-channel stages for decimated (uint16) ranges."""
     f = np.linspace(750.0, 550.0, 4096)
     coarse = sdd.Plan(f, 81.92e-6, dm_list=np.linspace(0.0, 1000.0, 2048))
     assert _share_fraction(coarse.delays(0)) < 0.5
@@ -354,4 +354,4 @@ def test_default_tiles_by_range():
     assert _share_fraction(multi.delays(0)) >= 0.5
     assert multi.get_tile(0) == (21, 2, 8, 1, 8, 8)
     for r in range(1, len(synth.MULTI_RANGES)):
-        assert multi.get_tile(r)[0] == 1
+        assert multi.get_tile(r) == (1, 2, 8, 1, 8, 4)
