@@ -138,8 +138,11 @@ sdd_status check_tile_fits(const sdd_plan* p, int32_t r, const sdd_tile& t, int3
 double range_share_fraction(const sdd_plan* p, int32_t r, int32_t dt) {
   const Range& R = p->ranges[r];
   const int32_t ndm = R.ndm(), C = p->nchan;
+  // at most about 2^22 groups are looked at: every step-th trial pair
+  const int64_t pairs = ndm / 2, per_pair = C / 2;
+  const int64_t step = std::max<int64_t>(1, pairs * per_pair >> 22);
   int64_t groups = 0, shared = 0;
-  for (int32_t i = 0; i + 1 < ndm; i += 2) {
+  for (int32_t i = 0; i + 1 < ndm; i += (int32_t)(2 * step)) {
     const int32_t i0 = i / dt * dt;
     if (i + 1 >= i0 + dt) continue;
     const int32_t* a = &R.delays[(size_t)i * C];
