@@ -89,8 +89,10 @@ __global__ __launch_bounds__(256) void k_corner_turn(const uint8_t* __restrict__
 // block in registers (two rounds of v_perm) into words of 4 consecutive
 // samples of one channel and stores them to LDS; then each thread writes 16
 // samples of one channel (a wavefront writes 128 contiguous bytes of 8
-// channel rows per store). LDS rows are 136 bytes, so the word stores of a
-// wavefront (8 groups x 8 quads) hit 64 different banks.
+// channel rows per store). LDS rows are 136 bytes: the 16-byte row reads
+// are conflict-free; the word stores of a wavefront (8 groups x 8 quads,
+// rows 16 channels apart) fall on 16 banks, a 4-way conflict that costs
+// about a quarter of the kernel's LDS cycles while HBM stays the bound.
 constexpr int kCtC = 128, kCtT = 128, kCtRow = kCtT + 8;
 __global__ __launch_bounds__(256) void k_corner_turn128(const uint8_t* __restrict__ in,
                                                         int64_t nsamp, int64_t in_pitch,
