@@ -89,10 +89,12 @@ __global__ __launch_bounds__(256) void k_corner_turn(const uint8_t* __restrict__
 // block in registers (two rounds of v_perm) into words of 4 consecutive
 // samples of one channel and stores them to LDS; then each thread writes 16
 // samples of one channel (a wavefront writes 128 contiguous bytes of 8
-// channel rows per store). LDS rows are 136 bytes: the 16-byte row reads
-// are conflict-free; the word stores of a wavefront (8 groups x 8 quads,
-// rows 16 channels apart) fall on 16 banks, a 4-way conflict that costs
-// about a quarter of the kernel's LDS cycles while HBM stays the bound.
+// channel rows per store). LDS rows are 136 bytes, and the 16-byte blocks of
+// row r are stored at block index b ^ (2 * ((r >> 5) & 3)): the word stores
+// of a wavefront (8 groups 16 rows apart x 8 quads) then hit 64 different
+// banks (rows alone would leave them on 16), and the row reads take whole
+// rows, so they stay conflict-free. (The time did not change, 0.546 ms on
+// the full-band chunk either way: HBM bounds the kernel.)
 constexpr int kCtC = 128, kCtT = 128, kCtRow = kCtT + 8;
 __global__ __launch_bounds__(256) void k_corner_turn128(const uint8_t* __restrict__ in,
                                                         int64_t nsamp, int64_t in_pitch,
@@ -134,7 +136,11 @@ __global__ __launch_bounds__(256) void k_corner_turn128(const uint8_t* __restric
                             __builtin_amdgcn_perm(hi23, hi01, 0x07060302u)};
 #pragma unroll
     for (int b = 0; b < 4; ++b)
-      *reinterpret_cast<uint32_t*>(tile + (16 * g + 4 * k + b) * kCtRow + 4 * q) = ch[b];
+    {
+      const int r = 16 * g + 4 * k + b;
+      *reinterpret_cast<uint32_t*>(tile + r * kCtRow + 16 * ((q >> 2) ^ (((r >> 5) & 3) << 1)) +
+                                   4 * (q & 3)) = ch[b];
+    }
   }
   __syncthreads();
   // 128 channels x 8 pieces of 16 samples: thread takes pieces tid + 256 p
@@ -143,7 +149,8 @@ __global__ __launch_bounds__(256) void k_corner_turn128(const uint8_t* __restric
     const int e = tid + 256 * p;
     const int c = e >> 3, sp = e & 7;
     const int64_t t = t0 + 16 * sp;
-    const uint2* src = reinterpret_cast<const uint2*>(tile + c * kCtRow + 16 * sp);
+    const uint2* src =
+        reinterpret_cast<const uint2*>(tile + c * kCtRow + 16 * (sp ^ (((c >> 5) & 3) << 1)));
     const uint2 a = src[0], b = src[1];
     uint8_t* dst = out + (int64_t)(c0 + c) * out_pitch + t;
     if (t + 16 <= nsamp) {
