@@ -38,7 +38,10 @@ __device__ __forceinline__ void mf_tile_impl(const LdsArgs& a, int32_t dtile, in
   constexpr int NE = (CS / 2) * D;  // (channel pair, trial) entries per wavefront and stage
   static_assert(CS % 2 == 0, "channels are taken in pairs");
   static_assert(NE <= 64, "one entry per lane");
-  static_assert(CS <= kDelayRowPad, "stage wider than the delay-table padding");
+  // The last stage is padded with empty channels up to CS, and their delay
+  // rows are read unmasked: the table's zero rows (to a multiple of
+  // kDelayRowPad) must cover every padded stage, so CS must divide it.
+  static_assert(kDelayRowPad % CS == 0, "stage must divide the delay-table padding");
   static_assert(CS * (TT + 32) <= 16 * NLD * NT, "staging too small for the tile");
   const int32_t i0 = dtile * DT;
   const int64_t t0 = (int64_t)ttile * TT;
