@@ -151,7 +151,10 @@ typedef struct sdd_dm_stats {  /* moments of the owned samples of one trial */
  * kind 1 + flags: LDS-tiled kernel (Section 3.2's brute-force sum, staged
  * per channel window in LDS). kind 1: vector form (byte align + widen with
  * v_perm, two channels per v_add3 into 16-bit fields); kind 3: the same
- * with two 64-bit LDS reads per 8 samples instead of 64 + 32 bits; kind 5:
+ * with two 64-bit LDS reads per 8 samples instead of 64 + 32 bits; kind 9:
+ * vector form for uint16 ranges (decimation > 1 only) that keeps four copies
+ * of each window, shifted by 0, 2, 4 and 6 bytes, so each channel costs one
+ * aligned 64-bit read and no v_perm per 4 samples; kind 5:
  * matrix-core form (the shifted channel sum as an int8 product with a 0/1
  * selection matrix, two channels per v_mfma_i32_16x16x64_i8, int32 sums;
  * uint8 ranges only); kind 21: kind 5 that reads a channel pair's data words

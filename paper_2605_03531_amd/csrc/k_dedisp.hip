@@ -58,7 +58,7 @@ int lds_args_for(const DedispArgs& a, LdsArgs* out) {
   const int es = a.elem_bytes;
   const int32_t flush = lds_flush_period(sh, a.max_val);
   if (es < 1 || es > 2 || flush < sh.cs) return -1;
-  if ((sh.f & 4) != 0 && es != 1) return -1;
+  if (!lds_shape_takes(sh, es)) return -1;
   LdsArgs& l = *out;
   l = LdsArgs{};
   l.x = (const uint8_t*)a.x;
@@ -81,8 +81,9 @@ int lds_args_for(const DedispArgs& a, LdsArgs* out) {
   const int64_t stage_bytes = (int64_t)sh.cs * a.x_pitch * es + l.win + 32 + (int64_t)es * a.max_delay;
   if (stage_bytes >= ((int64_t)1 << 32)) return -1;
   // tile t is interior when its last staging byte, es*(t*tt + max_delay) +
-  // win + 4, is inside the row
-  const int64_t room = (int64_t)es * (a.x_len - a.max_delay) - l.win - 4;
+  // win + 4 (+ 8 with four copies), is inside the row
+  const int64_t room =
+      (int64_t)es * (a.x_len - a.max_delay) - l.win - ((sh.f & 8) != 0 ? 8 : 4);
   int64_t n_int = 0;
   if (l.aligned && room >= 0) n_int = room / ((int64_t)es * tt) + 1;
   l.n_tt_interior = (int32_t)std::min<int64_t>(n_int, l.n_ttiles);

@@ -34,7 +34,9 @@ struct LdsShape {
   int nld;    // 16-byte staging loads per thread per stage
   int f;      // variant flags: 2 = third word through a 64-bit read,
               // 4 = matrix-core form (uint8 rows), 4 | 16 = matrix-core form
-              // that skips the data reads neighbouring trials share
+              // that skips the data reads neighbouring trials share,
+              // 8 = vector form with four shifted copies per window (uint16
+              // rows)
 };
 
 // Samples one tile of a shape covers for elements of es bytes.
@@ -48,9 +50,17 @@ inline int32_t lds_flush_period(const LdsShape& sh, int32_t max_val) {
 
 // LDS bytes of one workgroup for windows of win bytes (the kernel's own
 // sizing: two stage buffers of cs windows, two copies of each in the vector
-// form; one copy and a 1 KiB selection table in the matrix-core form).
+// form, four with flag 8; one copy and a 1 KiB selection table in the
+// matrix-core form).
 inline int64_t lds_tile_bytes(const LdsShape& sh, int64_t win) {
-  return (sh.f & 4) != 0 ? 2 * (int64_t)sh.cs * win + 1024 : 4 * (int64_t)sh.cs * win;
+  if ((sh.f & 4) != 0) return 2 * (int64_t)sh.cs * win + 1024;
+  return 2 * (int64_t)sh.cs * ((sh.f & 8) != 0 ? 4 : 2) * win;
+}
+// Whether a shape's form takes rows of es-byte elements.
+inline bool lds_shape_takes(const LdsShape& sh, int es) {
+  if ((sh.f & 4) != 0) return es == 1;
+  if ((sh.f & 8) != 0) return es == 2;
+  return es == 1 || es == 2;
 }
 
 // Sharing matrix-core shapes (flag 16) are the default for a range when at

@@ -36,6 +36,11 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 // (four 16-bit pairs after widening) or 4 uint16 samples (two pairs as read).
 // INTERIOR: every staging load of the tile lies inside the rows and the rows
 // are 16-byte aligned, so the loads need no per-element checks.
+// Flag 8 (uint16 rows only): each window is kept as four copies shifted by 0,
+// 2, 4 and 6 bytes, so every sample position a lane reads starts an aligned
+// 8-byte word of one of them: a channel costs one conflict-free 64-bit read
+// and two packed adds per 4 samples, where two copies (0 and 4 bytes) need a
+// 2-way bank-conflicted 32-bit read and two v_perm alignments as well.
 template <int D, int M, int WD, int WT, int CS, int NLD, int F, int ES, bool INTERIOR>
 __device__ __forceinline__ void dd_tile_impl(const LdsArgs& a, int32_t dtile, int32_t ttile,
                                              uint8_t* __restrict__ lds) {
@@ -47,6 +52,10 @@ __device__ __forceinline__ void dd_tile_impl(const LdsArgs& a, int32_t dtile, in
   constexpr int TW = CH * M;        // samples per time group of waves
   constexpr int TT = TW * WT;
   constexpr bool WIDE = (F & 2) != 0;  // third word through a 64-bit read
+  constexpr bool FOUR = (F & 8) != 0;  // four shifted copies per window
+  constexpr int NCOPY = FOUR ? 4 : 2;
+  static_assert(!FOUR || ES == 2, "four-copy windows hold uint16 rows");
+  static_assert(!FOUR || !WIDE, "four-copy windows read whole words");
   constexpr int NDV = (CS * D + 63) / 64;  // VGPRs holding one stage's read positions
   static_assert(CS % 2 == 0, "channels are added in pairs");
   // the staging must hold a stage's windows at zero delay span at least
@@ -60,7 +69,7 @@ __device__ __forceinline__ void dd_tile_impl(const LdsArgs& a, int32_t dtile, in
   const int wd = wave % WD, wt = wave / WD;
   const int32_t ndm = a.ndm, nchan = a.nchan;
   const int32_t win = a.win;            // bytes per copy, multiple of 16
-  const int32_t slot = 2 * win;         // copy 0 + copy 1
+  const int32_t slot = NCOPY * win;     // the copies of one window
   const int32_t buf = CS * slot;
   const int32_t wq = win >> 4;          // 16-byte elements per window
   const int64_t pitch_bytes = (int64_t)ES * a.x_pitch;
@@ -109,8 +118,11 @@ __device__ __forceinline__ void dd_tile_impl(const LdsArgs& a, int32_t dtile, in
   static_assert(CS <= kDelayRowPad, "stage wider than the delay-table padding");
 
   // copy 0 and copy 1 of each element as loaded (copy 1 is the same window
-  // 4 bytes on: a second 16-byte load from L1 costs no register moves)
+  // 4 bytes on: a second 16-byte load from L1 costs no register moves); with
+  // four copies, bytes 0-15 and 8-23 of the element, from which the copies
+  // are formed at the store
   u32x4 st0[NLD], st1[NLD];
+  constexpr int LB = FOUR ? 24 : 20;  // bytes of the row an element loads
   // d(c, i0) of each element's channel at a stage
   auto load_bases = [&](int32_t s, int32_t (&dst)[NLD]) {
     const uint8_t* row = ds + (int64_t)s * stage_drow;
@@ -127,21 +139,25 @@ __device__ __forceinline__ void dd_tile_impl(const LdsArgs& a, int32_t dtile, in
       const uint8_t* src = row + off;
       if constexpr (INTERIOR) {
         st0[k] = *reinterpret_cast<const u32x4*>(src);
-        st1[k] = *reinterpret_cast<const u32x4*>(src + 4);
+        st1[k] = *reinterpret_cast<const u32x4*>(src + (LB == 24 ? 8 : 4));
       } else {
         // byte g of the row; zero past its end
         const int64_t g = ES * (t0 + (bases[k] & ~15)) + eq16[k];
-        uint32_t w[5] = {0u, 0u, 0u, 0u, 0u};
-        if (a.aligned && g + 20 <= row_bytes) {
+        uint32_t w[LB / 4] = {};
+        if (a.aligned && g + LB <= row_bytes) {
           const uint4 t = *reinterpret_cast<const uint4*>(src);
           w[0] = t.x; w[1] = t.y; w[2] = t.z; w[3] = t.w;
           w[4] = *reinterpret_cast<const uint32_t*>(src + 16);
+          if constexpr (LB == 24) w[5] = *reinterpret_cast<const uint32_t*>(src + 20);
         } else {
-          for (int bb = 0; bb < 20; ++bb)
+          for (int bb = 0; bb < LB; ++bb)
             if (g + bb < row_bytes) w[bb >> 2] |= (uint32_t)src[bb] << (8 * (bb & 3));
         }
         st0[k] = u32x4{w[0], w[1], w[2], w[3]};
-        st1[k] = u32x4{w[1], w[2], w[3], w[4]};
+        if constexpr (LB == 24)
+          st1[k] = u32x4{w[2], w[3], w[4], w[5]};
+        else
+          st1[k] = u32x4{w[1], w[2], w[3], w[4]};
       }
     }
   };
@@ -151,9 +167,22 @@ __device__ __forceinline__ void dd_tile_impl(const LdsArgs& a, int32_t dtile, in
     for (int k = 0; k < NLD; ++k) {
       if (ecs[k] < CS) {
         uint8_t* c0 = base + elds[k];
-        // copy 0 as loaded; copy 1 byte j = window byte j + 4
-        *reinterpret_cast<u32x4*>(c0) = st0[k];
-        *reinterpret_cast<u32x4*>(c0 + win) = st1[k];
+        if constexpr (FOUR) {
+          // copy n byte j = window byte j + 2n, from words w0-w5 of the element
+          const uint32_t w0 = st0[k].x, w1 = st0[k].y, w2 = st0[k].z, w3 = st0[k].w;
+          const uint32_t w4 = st1[k].z, w5 = st1[k].w;
+          // bytes 2-5 of the pair (lo, hi)
+          auto mid = [](uint32_t lo, uint32_t hi) { return (lo >> 16) | (hi << 16); };
+          const uint32_t h1 = mid(w1, w2), h2 = mid(w2, w3), h3 = mid(w3, w4);
+          *reinterpret_cast<u32x4*>(c0) = st0[k];
+          *reinterpret_cast<u32x4*>(c0 + win) = u32x4{mid(w0, w1), h1, h2, h3};
+          *reinterpret_cast<u32x4*>(c0 + 2 * win) = u32x4{w1, w2, w3, w4};
+          *reinterpret_cast<u32x4*>(c0 + 3 * win) = u32x4{h1, h2, h3, mid(w4, w5)};
+        } else {
+          // copy 0 as loaded; copy 1 byte j = window byte j + 4
+          *reinterpret_cast<u32x4*>(c0) = st0[k];
+          *reinterpret_cast<u32x4*>(c0 + win) = st1[k];
+        }
       }
     }
   };
@@ -174,8 +203,10 @@ __device__ __forceinline__ void dd_tile_impl(const LdsArgs& a, int32_t dtile, in
   // Read positions of a stage: lane k < CS*D holds entry k = slot*D + d,
   // trial d of this wavefront in that slot's channel, packed as bits 0-19 the
   // LDS byte offset of its 8-byte word from the stage buffer (the slot's
-  // offset, plus copy 1 when the offset within the word is >= 4; at most
-  // CS * 2 * win < 80 KiB) and bits 20-21 the remaining byte shift.
+  // offset, plus the copy that starts the word at the position: copy 1 when
+  // the offset within the word is >= 4, or copy (offset within the word) / 2
+  // of four; at most CS * NCOPY * win < 160 KiB) and bits 20-21 the remaining
+  // byte shift (always 0 with four copies).
   // They are computed here across the lanes, once per stage, so the compute
   // loop needs one v_readlane and a few scalar operations per channel and
   // trial, and no scalar-memory waits that would also drain its LDS reads.
@@ -205,8 +236,12 @@ __device__ __forceinline__ void dd_tile_impl(const LdsArgs& a, int32_t dtile, in
 #pragma unroll
     for (int v = 0; v < NDV; ++v) {
       const int32_t o = ES * (rdv[v] - (rd0[v] & ~15));
-      const int32_t ad = (o & ~7) + ((o & 4) ? win : 0);
-      out[v] = (sl_off[v] + ad) | ((o & 3) << 20);
+      if constexpr (FOUR) {
+        out[v] = sl_off[v] + (o & ~7) + ((o >> 1) & 3) * win;
+      } else {
+        const int32_t ad = (o & ~7) + ((o & 4) ? win : 0);
+        out[v] = (sl_off[v] + ad) | ((o & 3) << 20);
+      }
     }
   };
 
@@ -234,11 +269,21 @@ __device__ __forceinline__ void dd_tile_impl(const LdsArgs& a, int32_t dtile, in
     r.sB0 = ES == 1 ? 0x0c010c00u + rB * 0x00010001u : 0x03020100u + rB * 0x01010101u;
 #pragma unroll
     for (int m = 0; m < M; ++m) {
-      const uint8_t* pA = bufp + adA + 512 * m;
-      const uint8_t* pB = bufp + adB + 512 * m;
+      int32_t oA = adA + 512 * m, oB = adB + 512 * m;
+      if constexpr (FOUR) {
+        // A register address per chunk: with one base and offsets 512 apart
+        // the compiler fuses the chunks' reads into one ds_read2st64_b64,
+        // which moves half the bytes per clock of two ds_read_b64.
+        if (m > 0) asm volatile("" : "+s"(oA), "+s"(oB));
+      }
+      const uint8_t* pA = bufp + oA;
+      const uint8_t* pB = bufp + oB;
       r.a01[m] = *reinterpret_cast<const uint2*>(pA);
       r.b01[m] = *reinterpret_cast<const uint2*>(pB);
-      if constexpr (WIDE) {
+      if constexpr (FOUR) {
+        // the word holds the lane's 4 samples in place
+        r.a2[m] = r.b2[m] = 0u;
+      } else if constexpr (WIDE) {
         const uint2 a23 = *reinterpret_cast<const uint2*>(pA + 8);
         const uint2 b23 = *reinterpret_cast<const uint2*>(pB + 8);
         // keep the full 64-bit reads (conflict-free at an 8-byte lane stride)
@@ -260,7 +305,10 @@ __device__ __forceinline__ void dd_tile_impl(const LdsArgs& a, int32_t dtile, in
     for (int m = 0; m < M; ++m) {
       const uint2 a01 = r.a01[m], b01 = r.b01[m];
       const uint32_t a2 = r.a2[m], b2 = r.b2[m];
-      if constexpr (ES == 1) {
+      if constexpr (FOUR) {
+        acc[d][m][0] += a01.x + b01.x;
+        acc[d][m][1] += a01.y + b01.y;
+      } else if constexpr (ES == 1) {
         acc[d][m][0] += __builtin_amdgcn_perm(a01.y, a01.x, sA0) +
                         __builtin_amdgcn_perm(b01.y, b01.x, sB0);
         acc[d][m][1] += __builtin_amdgcn_perm(a01.y, a01.x, sA2) +
@@ -382,11 +430,14 @@ __device__ __forceinline__ void dd_tile_impl(const LdsArgs& a, int32_t dtile, in
 
 // Shapes with flag 4 take the matrix-core form (uint8 rows only; its
 // launchers refuse uint16 jobs), with M 512-sample chunks = 2 M products of
-// 256 samples per trial and wavefront.
+// 256 samples per trial and wavefront; shapes with flag 8 take uint16 rows
+// only.
 template <int D, int M, int WD, int WT, int CS, int NLD, int F, int ES>
 __device__ __forceinline__ void dd_tile(const LdsArgs& a, int32_t dtile, int32_t ttile,
                                         uint8_t* __restrict__ lds) {
-  if constexpr ((F & 4) != 0) {
+  if constexpr ((F & 8) != 0 && ES != 2) {
+    // four-copy shapes take uint16 rows only; their launchers refuse the rest
+  } else if constexpr ((F & 4) != 0) {
     constexpr bool SHARE = (F & 16) != 0;
     if (ttile < a.n_tt_interior)
       mf_tile_impl<D, 2 * M, WD, WT, CS, NLD, true, SHARE>(a, dtile, ttile, lds);
@@ -409,11 +460,18 @@ template <int F>
 constexpr int kWavesPerSimd = (F & 4) != 0 ? 4 : 1;
 
 // Dynamic LDS of one workgroup: two stage buffers of CS windows, with two
-// copies per window in the vector form, one plus the 1 KiB selection table
-// in the matrix-core form.
+// copies per window in the vector form (four with flag 8), one plus the 1 KiB
+// selection table in the matrix-core form.
 template <int CS, int F>
 constexpr size_t tile_lds_bytes(int32_t win) {
-  return (F & 4) != 0 ? (size_t)2 * CS * win + 1024 : (size_t)2 * CS * 2 * win;
+  return (F & 4) != 0 ? (size_t)2 * CS * win + 1024
+                      : (size_t)2 * CS * ((F & 8) != 0 ? 4 : 2) * win;
+}
+// The kinds of rows a shape's form takes: the matrix-core form uint8 only,
+// the four-copy vector form uint16 only.
+template <int F, int ES>
+constexpr bool takes_rows() {
+  return (F & 4) != 0 ? ES == 1 : (F & 8) != 0 ? ES == 2 : true;
 }
 
 // Grid form: one workgroup per tile of one job, ordered time-tile-major with a
@@ -465,7 +523,7 @@ __global__ __launch_bounds__(64 * WD * WT, kWavesPerSimd<F>) void k_dedisp_lds_m
 template <int D, int M, int WD, int WT, int CS, int NLD, int F, int ES>
 hipError_t launch_multi(const MultiArgs& m, int32_t max_win, hipStream_t s) {
   constexpr int NT = 64 * WD * WT;
-  if ((F & 4) != 0 && ES != 1) return hipErrorInvalidValue;
+  if (!takes_rows<F, ES>()) return hipErrorInvalidValue;
   const size_t lds = tile_lds_bytes<CS, F>(max_win);
   auto kern = k_dedisp_lds_multi<D, M, WD, WT, CS, NLD, F, ES>;
   if (lds > 65536) {
@@ -489,7 +547,7 @@ hipError_t launch_multi(const MultiArgs& m, int32_t max_win, hipStream_t s) {
 template <int D, int M, int WD, int WT, int CS, int NLD, int F, int ES>
 hipError_t launch_one(const LdsArgs& a, hipStream_t s) {
   constexpr int NT = 64 * WD * WT;
-  if ((F & 4) != 0 && ES != 1) return hipErrorInvalidValue;
+  if (!takes_rows<F, ES>()) return hipErrorInvalidValue;
   const size_t lds = tile_lds_bytes<CS, F>(a.win);
   auto kern = k_dedisp_lds<D, M, WD, WT, CS, NLD, F, ES>;
   if (lds > 65536) {
@@ -525,7 +583,10 @@ hipError_t launch_one(const LdsArgs& a, hipStream_t s) {
   X(1, 4, 8, 1, 4, 2, 0)       \
   X(4, 1, 8, 2, 4, 1, 0)       \
   X(4, 1, 16, 1, 4, 1, 0)      \
-  X(8, 1, 4, 1, 8, 4, 0)
+  X(8, 1, 4, 1, 8, 4, 0)       \
+  X(4, 2, 8, 1, 4, 1, 8)       \
+  X(2, 2, 8, 1, 4, 1, 8)       \
+  X(8, 1, 8, 1, 4, 1, 8)
 
 #define SDD_SHAPE_ROW(d, m, wd, wt, cs, nld, f) {d, m, wd, wt, cs, nld, f},
 #define SDD_ONE_PTR(d, m, wd, wt, cs, nld, f) \

@@ -148,11 +148,23 @@ def test_compute_calls_validate_before_touching_the_device():
 def test_tile_menu_and_set_tile():
     menu = sdd.tile_menu()
     assert (0, 0, 0, 0, 0, 0) in menu
-    # a delay span of 15 samples fits every shape's staging
+    # a delay span of 15 samples fits every shape's staging; the matrix-core
+    # form (flag 4: kinds 5, 21) takes uint8 rows only, the aligned-word
+    # vector form (flag 8: kind 9) uint16 rows (a decimated range) only
     p = sdd.Plan([500.0, 300.0], 1e-3, dm_list=[0.0, 0.5])
+    q = sdd.Plan([500.0, 300.0], 1e-3, ranges=[(0.0, 1.0, 0.5, 2)])
     for t in menu:
-        p.set_tile(t)
-        assert p.get_tile(0) == t
+        flags = t[0] - 1 if t[0] else 0  # kind 0: the direct kernel
+        u8_ok = not flags & 8
+        u16_ok = not flags & 4
+        for plan, ok in ((p, u8_ok), (q, u16_ok)):
+            if ok:
+                plan.set_tile(t, 0)
+                assert plan.get_tile(0) == t
+            else:
+                with pytest.raises(sdd.SddError):
+                    plan.set_tile(t, 0)
+    assert any(t[0] == 9 for t in menu)
     with pytest.raises(sdd.SddError):
         p.set_tile((9, 9, 9, 9, 9, 9))
 
@@ -345,7 +357,9 @@ def test_default_tiles_by_range():
     """The plan's default tile per range: the matrix-core form for uint8
     ranges, its read-sharing variant where at least half of the groups of
     neighbouring trials start in the same data words (fine DM steps), the
-    vector form with 4-channel stages for decimated (uint16) ranges."""
+    four-copy vector form for decimated (uint16) ranges, and the two-copy
+    vector form for a decimated range whose delay span is too wide for the
+    four-copy staging."""
     f = np.linspace(750.0, 550.0, 4096)
     coarse = sdd.Plan(f, 81.92e-6, dm_list=np.linspace(0.0, 1000.0, 2048))
     assert _share_fraction(coarse.delays(0)) < 0.5
@@ -354,4 +368,8 @@ def test_default_tiles_by_range():
     assert _share_fraction(multi.delays(0)) >= 0.5
     assert multi.get_tile(0) == (21, 2, 8, 1, 8, 8)
     for r in range(1, len(synth.MULTI_RANGES)):
-        assert multi.get_tile(r) == (1, 2, 8, 1, 8, 4)
+        assert multi.get_tile(r) == (9, 4, 8, 1, 8, 4)
+    # DM 0-300 in 300 trials at decimation 2: about 2500 samples of delay
+    # span per 64 trials, past every four-copy shape's staging
+    wide = sdd.Plan(np.linspace(750.0, 550.0, 999), 81.92e-6, ranges=[(0.0, 300.0, 1.0, 2)])
+    assert wide.get_tile(0)[0] == 1

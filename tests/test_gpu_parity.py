@@ -112,13 +112,11 @@ def test_multi_range_small_full_plane():
         ph, res, g = gpu_run(plan, x, time_major=(layout == "time"))
         compare_rows(spec, ph, orc)
         compare_search(spec, res, orc, full_rows=True)
-    # every tile shape, on all ranges (uint8 and uint16 inputs)
+    # every tile shape, on each range that takes it (uint8 and uint16 inputs)
     plan = _make(kw, "time")
     n = 0
     for tile in _menu_tiles():
-        try:
-            plan.set_tile(tile)
-        except Exception:
+        if not _set_where_it_fits(plan, tile):
             continue
         ph, res, g = gpu_run(plan, x, time_major=True)
         compare_rows(spec, ph, orc)
@@ -333,19 +331,38 @@ def _menu_tiles():
     return sdd.tile_menu()
 
 
+def _set_where_it_fits(plan, tile):
+    """Sets `tile` on every range that takes it (the matrix-core shapes take
+    uint8 rows only, the four-copy shapes uint16 rows only); the other ranges
+    keep their tile. Returns the ranges set."""
+    done = []
+    for r in range(plan.nranges):
+        try:
+            plan.set_tile(tile, r)
+        except Exception:
+            continue
+        done.append(r)
+    return done
+
+
 def test_every_tile_shape_is_exact():
     """Each kernel shape of the built menu gives the oracle's plane on a
     ragged case: 999 channels (odd, and not a multiple of any stage, so the
     last channels are added past the staged loop), 300 trials (a partial DM
     tile), a partial time tile and a padded spectra pitch. A wide DM range
     exercises large delay spans; a narrow one fits the shapes whose staging
-    holds only small spans, so every shape runs on at least one of them."""
+    holds only small spans, so every shape runs on at least one of them.
+    Each case runs on uint8 rows (a plain trial list) and on the uint16 rows
+    of a range decimated by 2, which the four-copy shapes take."""
     f = np.linspace(750.0, 550.0, 999)
     ran = set()
-    for dm_hi in (300.0, 12.0):
-        dms = np.linspace(0.0, dm_hi, 300)
-        kw = dict(freqs_mhz=f, t_samp=81.92e-6, dm_list=dms)
+    for dm_hi, dec in ((300.0, 1), (12.0, 1), (300.0, 2), (12.0, 2)):
+        if dec == 1:
+            kw = dict(freqs_mhz=f, t_samp=81.92e-6, dm_list=np.linspace(0.0, dm_hi, 300))
+        else:
+            kw = dict(freqs_mhz=f, t_samp=81.92e-6, ranges=[(0.0, dm_hi, dm_hi / 300, dec)])
         spec = oracle_plan(kw)
+        assert spec.ranges[0].dms.size == 300
         T = spec.overlap + 3 * 1024 + 77
         x = synth.filterbank(31, 999, T, 128.0, 16.0)
         rows = [0, 1, 63, 64, 150, 255, 256, 298, 299]
@@ -356,9 +373,9 @@ def test_every_tile_shape_is_exact():
             try:
                 plan.set_tile(tile)
             except Exception:
-                say(f"DM 0-{dm_hi}: tile {tile} does not fit this plan")
+                say(f"DM 0-{dm_hi}, decimation {dec}: tile {tile} does not fit this plan")
                 continue
-            say(f"DM 0-{dm_hi}: tile {tile}")
+            say(f"DM 0-{dm_hi}, decimation {dec}: tile {tile}")
             ph, _, g = gpu_run(plan, x, search=False, time_major=True)
             assert (ph[0][rows].astype(np.int64) == yo).all(), tile
             seen.append(ph[0])
@@ -410,9 +427,7 @@ def test_saturated_input_every_tile_grid_and_persistent():
     plan = _make(kw, "time")
     ran = 0
     for tile in _menu_tiles():
-        try:
-            plan.set_tile(tile)
-        except Exception:
+        if not _set_where_it_fits(plan, tile):
             continue
         ran += 1
         for name, x in inputs.items():
