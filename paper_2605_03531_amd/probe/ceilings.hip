@@ -70,6 +70,83 @@ __global__ __launch_bounds__(kNt) void k_rd128(uint32_t* out) {
   out[blockIdx.x * kNt + threadIdx.x] = acc;
 }
 
+// Two 8-byte words 512 bytes apart per lane (ds_read2st64_b64, the form the
+// compiler fuses two ds_read_b64 of one base into), 8 independent, then a wait.
+__global__ __launch_bounds__(kNt) void k_rd2st64(uint32_t* out) {
+  __shared__ __attribute__((aligned(16))) uint8_t lds[32768];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int i = threadIdx.x; i < 32768 / 4; i += kNt) reinterpret_cast<uint32_t*>(lds)[i] = i;
+  __syncthreads();
+  // base below 4 KiB + 8; reads end below 12 KiB
+  const uint32_t a0 = (uint32_t)(uintptr_t)lds + 8 * lane + 512 * w;
+  uint32_t acc = 0, x = 0;
+  for (int it = 0; it < kIter; ++it) {
+    u32x4 r0, r1, r2, r3, r4, r5, r6, r7;
+    const uint32_t b0 = a0 + x, b1 = b0 + 1024, b2 = b0 + 2048, b3 = b0 + 3072, b4 = b0 + 4096,
+                   b5 = b0 + 5120, b6 = b0 + 6144, b7 = b0 + 7168;
+    asm volatile(
+        "ds_read2st64_b64 %0, %8 offset0:0 offset1:1\n ds_read2st64_b64 %1, %9 offset0:0 offset1:1\n"
+        "ds_read2st64_b64 %2, %10 offset0:0 offset1:1\n ds_read2st64_b64 %3, %11 offset0:0 offset1:1\n"
+        "ds_read2st64_b64 %4, %12 offset0:0 offset1:1\n ds_read2st64_b64 %5, %13 offset0:0 offset1:1\n"
+        "ds_read2st64_b64 %6, %14 offset0:0 offset1:1\n ds_read2st64_b64 %7, %15 offset0:0 offset1:1\n"
+        "s_waitcnt lgkmcnt(0)\n"
+        : "=v"(r0), "=v"(r1), "=v"(r2), "=v"(r3), "=v"(r4), "=v"(r5), "=v"(r6), "=v"(r7)
+        : "v"(b0), "v"(b1), "v"(b2), "v"(b3), "v"(b4), "v"(b5), "v"(b6), "v"(b7));
+    acc += r0.x ^ r1.y ^ r2.z ^ r3.w ^ r4.x ^ r5.y ^ r6.z ^ r7.w;
+    x ^= 8;
+  }
+  out[blockIdx.x * kNt + threadIdx.x] = acc;
+}
+
+// Two dwords 4 bytes into each 8-byte lane slot (ds_read2_b32: a 64-bit read
+// at 4-byte alignment), 8 independent, then a wait.
+__global__ __launch_bounds__(kNt) void k_rd2b32(uint32_t* out) {
+  __shared__ __attribute__((aligned(16))) uint8_t lds[32768];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int i = threadIdx.x; i < 32768 / 4; i += kNt) reinterpret_cast<uint32_t*>(lds)[i] = i;
+  __syncthreads();
+  // base below 4 KiB + 8; reads end below 8 KiB
+  const uint32_t a0 = (uint32_t)(uintptr_t)lds + 8 * lane + 512 * w;
+  uint32_t acc = 0, x = 0;
+  for (int it = 0; it < kIter; ++it) {
+    u32x2 r0, r1, r2, r3, r4, r5, r6, r7;
+    const uint32_t b0 = a0 + x, b1 = b0 + 512, b2 = b0 + 1024, b3 = b0 + 1536, b4 = b0 + 2048,
+                   b5 = b0 + 2560, b6 = b0 + 3072, b7 = b0 + 3584;
+    asm volatile(
+        "ds_read2_b32 %0, %8 offset0:1 offset1:2\n ds_read2_b32 %1, %9 offset0:1 offset1:2\n"
+        "ds_read2_b32 %2, %10 offset0:1 offset1:2\n ds_read2_b32 %3, %11 offset0:1 offset1:2\n"
+        "ds_read2_b32 %4, %12 offset0:1 offset1:2\n ds_read2_b32 %5, %13 offset0:1 offset1:2\n"
+        "ds_read2_b32 %6, %14 offset0:1 offset1:2\n ds_read2_b32 %7, %15 offset0:1 offset1:2\n"
+        "s_waitcnt lgkmcnt(0)\n"
+        : "=v"(r0), "=v"(r1), "=v"(r2), "=v"(r3), "=v"(r4), "=v"(r5), "=v"(r6), "=v"(r7)
+        : "v"(b0), "v"(b1), "v"(b2), "v"(b3), "v"(b4), "v"(b5), "v"(b6), "v"(b7));
+    acc += r0.x ^ r1.y ^ r2.x ^ r3.y ^ r4.x ^ r5.y ^ r6.x ^ r7.y;
+    x ^= 8;
+  }
+  out[blockIdx.x * kNt + threadIdx.x] = acc;
+}
+
+// 8 independent ds_write_b64 at an 8-byte lane stride, then a wait.
+__global__ __launch_bounds__(kNt) void k_wr64(uint32_t* out) {
+  __shared__ __attribute__((aligned(16))) uint8_t lds[32768];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint32_t addr = (uint32_t)(uintptr_t)lds + 8 * lane + 512 * w;  // below 4 KiB
+  u32x2 v = {(uint32_t)threadIdx.x, 1u};
+  for (int it = 0; it < kIter; ++it) {
+    asm volatile(
+        "ds_write_b64 %0, %1 offset:0\n ds_write_b64 %0, %1 offset:4096\n"
+        "ds_write_b64 %0, %1 offset:8192\n ds_write_b64 %0, %1 offset:12288\n"
+        "ds_write_b64 %0, %1 offset:16384\n ds_write_b64 %0, %1 offset:20480\n"
+        "ds_write_b64 %0, %1 offset:24576\n ds_write_b64 %0, %1 offset:28672\n"
+        "s_waitcnt lgkmcnt(0)\n" ::"v"(addr),
+        "v"(v)
+        : "memory");
+    v.y += 1;
+  }
+  __syncthreads();
+  out[blockIdx.x * kNt + threadIdx.x] = reinterpret_cast<uint32_t*>(lds)[threadIdx.x];
+}
+
 // 8 independent ds_write_b128 at a 16-byte lane stride, then a wait.
 __global__ __launch_bounds__(kNt) void k_wr128(uint32_t* out) {
   __shared__ __attribute__((aligned(16))) uint8_t lds[32768];
@@ -174,6 +251,9 @@ int main() {
   } rows[] = {
       {"ds_read_b64", time_ms([&] { hipLaunchKernelGGL(k_rd64, dim3(kGrid), dim3(kNt), 0, 0, out); }), 8},
       {"ds_read_b128", time_ms([&] { hipLaunchKernelGGL(k_rd128, dim3(kGrid), dim3(kNt), 0, 0, out); }), 16},
+      {"ds_read2st64_b64", time_ms([&] { hipLaunchKernelGGL(k_rd2st64, dim3(kGrid), dim3(kNt), 0, 0, out); }), 16},
+      {"ds_read2_b32_4byte_aligned", time_ms([&] { hipLaunchKernelGGL(k_rd2b32, dim3(kGrid), dim3(kNt), 0, 0, out); }), 8},
+      {"ds_write_b64", time_ms([&] { hipLaunchKernelGGL(k_wr64, dim3(kGrid), dim3(kNt), 0, 0, out); }), 8},
       {"ds_write_b128", time_ms([&] { hipLaunchKernelGGL(k_wr128, dim3(kGrid), dim3(kNt), 0, 0, out); }), 16},
       {"v_add3_u32", time_ms([&] { hipLaunchKernelGGL(k_valu<false>, dim3(kGrid), dim3(kNt), 0, 0, out); }), 0},
       {"v_perm_b32", time_ms([&] { hipLaunchKernelGGL(k_valu<true>, dim3(kGrid), dim3(kNt), 0, 0, out); }), 0},
