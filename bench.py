@@ -587,8 +587,47 @@ def multi_range_bench(sdd, torch, steps: int, warmup: int):
                                     "frac": round(ct_bytes / stage["corner_turn"] / 1e6 / 8000.0,
                                                   4)},
            "candidates": int(out.ncand.cpu()[0])}
+    res["uint16_forms"] = uint16_forms(torch, plan, step, planes)
     log(f"multi-range: {res}")
     del x, planes, out, ws
+    return res
+
+
+def uint16_forms(torch, plan, step, planes, reps: int = 2):
+    """The multi-range step's dedispersion stage with the decimated (uint16)
+    ranges in the four-copy vector form (their default) and in the two-copy
+    vector form, and whether those ranges' planes are identical."""
+    import ctypes as C
+    from paper_2605_03531_amd import _capi as A
+    L = A.lib()
+    keep = [tuple(plan.get_tile(r)) for r in range(plan.nranges)]
+    u16 = [r for r in range(plan.nranges) if plan.decimation[r] > 1]
+    res, ref = {}, None
+    for name, tile in (("four_copy", None), ("two_copy", (1, 2, 8, 1, 8, 4))):
+        for r in u16:
+            plan.set_tile(tile if tile is not None else keep[r], r)
+        step()
+        torch.cuda.synchronize()
+        A.check(L.sdd_profile_enable(1), "profile")
+        for _ in range(reps):
+            step()
+        torch.cuda.synchronize()
+        ms, n = C.c_double(), C.c_int64()
+        A.check(L.sdd_profile_read(A.STAGES["dedisperse"], C.byref(ms), C.byref(n)), "read")
+        L.sdd_profile_enable(0)
+        same = None
+        if ref is None:
+            ref = [planes[r].clone() for r in u16]
+        else:
+            same = all(bool(torch.equal(ref[k], planes[r])) for k, r in enumerate(u16))
+        res[name] = {"tiles": [list(plan.get_tile(r)) for r in u16],
+                     "dedisperse_ms": round(ms.value / reps, 3),
+                     "planes_equal_to_four_copy": same}
+    for r in u16:
+        plan.set_tile(keep[r], r)
+    res["note"] = ("dedispersion of the whole step (range 0 unchanged in both); only the "
+                   "decimated ranges' tiles differ")
+    del ref
     return res
 
 
