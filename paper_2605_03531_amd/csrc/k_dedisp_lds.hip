@@ -432,6 +432,16 @@ __device__ __forceinline__ void dd_tile_impl(const LdsArgs& a, int32_t dtile, in
 // launchers refuse uint16 jobs), with M 512-sample chunks = 2 M products of
 // 256 samples per trial and wavefront; shapes with flag 8 take uint16 rows
 // only.
+// Reads the matrix-core loop keeps in flight ahead of its products (0: the
+// compiler's order), measured per shape on the full-band chunk: the
+// one-trial, 2048-sample, 16-channel-stage shape 51.9 ms with 4 against 55.6
+// ms with 0 (3: 52.5, 5: 52.1), and its persistent form over 32 beams 1.070 s
+// with 4 against 1.074 (3), 1.103 (2) and 1.128 s (0), though it keeps 64
+// bytes per lane in scratch at 4; the two-trial shapes spill from 4 on and
+// were no faster with 2 or 3, so they keep 0.
+template <int D, int M, int CS>
+constexpr int kMfAhead = (D == 1 && M == 4 && CS == 16) ? 4 : 0;
+
 template <int D, int M, int WD, int WT, int CS, int NLD, int F, int ES>
 __device__ __forceinline__ void dd_tile(const LdsArgs& a, int32_t dtile, int32_t ttile,
                                         uint8_t* __restrict__ lds) {
@@ -439,10 +449,11 @@ __device__ __forceinline__ void dd_tile(const LdsArgs& a, int32_t dtile, int32_t
     // four-copy shapes take uint16 rows only; their launchers refuse the rest
   } else if constexpr ((F & 4) != 0) {
     constexpr bool SHARE = (F & 16) != 0;
+    constexpr int AH = kMfAhead<D, M, CS>;
     if (ttile < a.n_tt_interior)
-      mf_tile_impl<D, 2 * M, WD, WT, CS, NLD, true, SHARE>(a, dtile, ttile, lds);
+      mf_tile_impl<D, 2 * M, WD, WT, CS, NLD, true, SHARE, AH>(a, dtile, ttile, lds);
     else
-      mf_tile_impl<D, 2 * M, WD, WT, CS, NLD, false, SHARE>(a, dtile, ttile, lds);
+      mf_tile_impl<D, 2 * M, WD, WT, CS, NLD, false, SHARE, AH>(a, dtile, ttile, lds);
   } else {
     if (ttile < a.n_tt_interior)
       dd_tile_impl<D, M, WD, WT, CS, NLD, F, ES, true>(a, dtile, ttile, lds);

@@ -24,11 +24,15 @@
 // Per wavefront: D trials x MT blocks of 256 samples; per (channel pair,
 // trial) one table read, MT 16-byte data reads and MT products. Staging
 // keeps one copy per channel (16-byte aligned windows), double-buffered by
-// stage as in the vector form.
+// stage as in the vector form. AHEAD > 0 pins the order of a stage's reads
+// and products with scheduling groups so that AHEAD reads are in flight
+// when a product issues (left alone, the compiler issues each read one or
+// two ahead of its product, too few to cover the LDS latency at 4
+// wavefronts per SIMD).
 
 typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
 
-template <int D, int MT, int WD, int WT, int CS, int NLD, bool INTERIOR, bool SHARE>
+template <int D, int MT, int WD, int WT, int CS, int NLD, bool INTERIOR, bool SHARE, int AHEAD>
 __device__ __forceinline__ void mf_tile_impl(const LdsArgs& a, int32_t dtile, int32_t ttile,
                                              uint8_t* __restrict__ lds) {
   constexpr int NT = 64 * WD * WT;
@@ -272,6 +276,22 @@ __device__ __forceinline__ void mf_tile_impl(const LdsArgs& a, int32_t dtile, in
       for (int e = 0; e < NE; ++e) {
         if (e + 1 < NE) fetch(ppc, rrc, e + 1, gr[(e + 1) & 1]);
         consume(e, gr[e & 1]);
+      }
+      if constexpr (AHEAD > 0) {
+        // The stage's order: the first group's selection read and AHEAD data
+        // reads, then one read after each product, two where the next group's
+        // selection read falls, so every product finds AHEAD reads issued
+        // past its own (masks: 0x100 LDS reads, 0x008 matrix products).
+        static_assert(AHEAD < MT, "look-ahead within a group");
+        __builtin_amdgcn_sched_group_barrier(0x100, 1 + AHEAD, 0);
+#pragma unroll
+        for (int t = 0; t < NE * MT; ++t) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+          if ((t % MT) == MT - 1 - AHEAD)
+            __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+          else
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+        }
       }
     }
     if (s + 1 < nstages) {
