@@ -59,7 +59,7 @@ LDS_PEAK_TBPS = 237 * 256 * 2.4e9 / 1e12
 # profiles/k_dedisp_mfma_full_band_hbm_bytes.md).
 # Valid for the tile shape it was taken with; any other shape reports null.
 MEASURED_TRAFFIC = {(1, 2, 8, 1, 8, 8): 61.13e9, (5, 2, 8, 1, 8, 16): 52.34e9,
-                    (5, 1, 16, 1, 16, 16): 29.74e9}
+                    (5, 1, 16, 1, 16, 16): 29.75e9}
 # Adds per VALU instruction of the vector form for that tile, from the SQ
 # counters (profiles/k_dedisp_vector_full_band_sq_counters.md)
 ADDS_PER_VALU = {(1, 2, 8, 1, 8, 8): 66.3}
