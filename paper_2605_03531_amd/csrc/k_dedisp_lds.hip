@@ -39,8 +39,9 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 // Flag 8 (uint16 rows only): each window is kept as four copies shifted by 0,
 // 2, 4 and 6 bytes, so every sample position a lane reads starts an aligned
 // 8-byte word of one of them: a channel costs one conflict-free 64-bit read
-// and two packed adds per 4 samples, where two copies (0 and 4 bytes) need a
-// 2-way bank-conflicted 32-bit read and two v_perm alignments as well.
+// per 4 samples, and a channel pair one v_add3 per packed word, where two
+// copies (0 and 4 bytes) need a 2-way bank-conflicted 32-bit read and two
+// v_perm alignments per channel as well.
 template <int D, int M, int WD, int WT, int CS, int NLD, int F, int ES, bool INTERIOR>
 __device__ __forceinline__ void dd_tile_impl(const LdsArgs& a, int32_t dtile, int32_t ttile,
                                              uint8_t* __restrict__ lds) {
@@ -428,10 +429,6 @@ __device__ __forceinline__ void dd_tile_impl(const LdsArgs& a, int32_t dtile, in
 
 #include "k_dedisp_mfma.h"
 
-// Shapes with flag 4 take the matrix-core form (uint8 rows only; its
-// launchers refuse uint16 jobs), with M 512-sample chunks = 2 M products of
-// 256 samples per trial and wavefront; shapes with flag 8 take uint16 rows
-// only.
 // Reads the matrix-core loop keeps in flight ahead of its products (0: the
 // compiler's order), measured per shape on the full-band chunk: the
 // one-trial, 2048-sample, 16-channel-stage shape 51.9 ms with 4 against 55.6
@@ -442,6 +439,10 @@ __device__ __forceinline__ void dd_tile_impl(const LdsArgs& a, int32_t dtile, in
 template <int D, int M, int CS>
 constexpr int kMfAhead = (D == 1 && M == 4 && CS == 16) ? 4 : 0;
 
+// Shapes with flag 4 take the matrix-core form (uint8 rows only; its
+// launchers refuse uint16 jobs), with M 512-sample chunks = 2 M products of
+// 256 samples per trial and wavefront; shapes with flag 8 take uint16 rows
+// only.
 template <int D, int M, int WD, int WT, int CS, int NLD, int F, int ES>
 __device__ __forceinline__ void dd_tile(const LdsArgs& a, int32_t dtile, int32_t ttile,
                                         uint8_t* __restrict__ lds) {
